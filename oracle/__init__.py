@@ -1,0 +1,178 @@
+"""CPU FP64 oracle for the reduced-basis greedy (arXiv 1805.06124).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+library (``paper_1805_06124_amd``) never imports it, and it never imports the
+product: the two share no code.  The only module both sides use is
+``rb_inputs`` (seeded parameter generators, none of the method's arithmetic).
+
+The arithmetic lives in ``rb_oracle.c`` (plain C99, FP64, compiled with gcc by
+``oracle/build.py``); this module is argument marshalling through ctypes, plus
+the FP64 MLP of ``oracle/mlp.py``.
+
+Array conventions: a complex N x M snapshot matrix is passed as a C-contiguous
+numpy ``complex128`` array of shape ``(M, N)`` (row j = column s_j), which is
+exactly the column-major N x M layout the C code reads.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "rb_oracle.c")
+
+STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -4: "ENONFINITE", -6: "EREPLAY"}
+
+
+def build(force: bool = False) -> str:
+    """Compile rb_oracle.c with gcc into liboracle.so (OpenMP on)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-o", tmp, SRC_PATH, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        L.oracle_sqnorm.restype = D
+        L.oracle_sqnorm.argtypes = [P, I64]
+        L.oracle_sqnorms.restype = None
+        L.oracle_sqnorms.argtypes = [P, I64, I64, I64, P]
+        L.oracle_chirp.restype = None
+        L.oracle_chirp.argtypes = [P, I64, D, D, I64, P, I64]
+        for name in ("oracle_greedy_explicit", "oracle_greedy_pythag"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [P, I64, I64, I64, D, I64, D, ctypes.c_int, P, I64,
+                          P, P, P, P, P, P, P, P]
+        L.oracle_project.restype = None
+        L.oracle_project.argtypes = [P, I64, I64, I64, P, I64, I64, P, I64]
+        L.oracle_residual_norms.restype = None
+        L.oracle_residual_norms.argtypes = [P, I64, I64, I64, P, I64, I64, P]
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _cmat(S) -> np.ndarray:
+    S = np.ascontiguousarray(S, dtype=np.complex128)
+    if S.ndim != 2:
+        raise ValueError("snapshot matrix must be 2-D (M, N)")
+    return S
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def sqnorm(x) -> float:
+    """||x||^2 accumulated exactly and rounded once."""
+    x = np.ascontiguousarray(x, dtype=np.complex128).ravel()
+    return float(lib().oracle_sqnorm(_ptr(x), x.size))
+
+
+def sqnorms(S) -> np.ndarray:
+    S = _cmat(S)
+    M, N = S.shape
+    out = np.empty(M, dtype=np.float64)
+    lib().oracle_sqnorms(_ptr(S), N, M, N, _ptr(out))
+    return out
+
+
+def chirp(params, N: int, flo: float, fhi: float) -> np.ndarray:
+    """Unit-norm chirp snapshots, shape (M, N) complex128; params (M, 2) = (Mtot [M_sun], q)."""
+    params = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 2)
+    M = params.shape[0]
+    out = np.empty((M, N), dtype=np.complex128)
+    lib().oracle_chirp(_ptr(params), M, float(flo), float(fhi), int(N), _ptr(out), int(N))
+    return out
+
+
+def greedy(S, tol: float, kmax: int, mode: str = "explicit", force=None, kappa: float = 2.0,
+           nu_max: int = 4, want_coeffs: bool = False) -> dict:
+    """Run the oracle greedy.
+
+    mode "explicit": Alg. 2 form (residual matrix), the reference definition.
+    mode "pythag"  : pivot search by the Eq. (6.3) update (the paper's code).
+    force          : optional pivot sequence to replay (forced-pivot mode).
+    Returns dict(E (k, N), piv (k,), err (k+1,), rho (k,), nu (k,),
+    pick (k, 2), C (k, M) or None, k, status).
+    """
+    S = _cmat(S)
+    M, N = S.shape
+    kcap = max(0, min(int(kmax), N, M))
+    E = np.zeros((max(kcap, 1), N), dtype=np.complex128)
+    piv = np.full(max(kcap, 1), -1, dtype=np.int64)
+    err = np.zeros(kcap + 1, dtype=np.float64)
+    rho = np.zeros(max(kcap, 1), dtype=np.float64)
+    nu = np.zeros(max(kcap, 1), dtype=np.int32)
+    pick = np.zeros((max(kcap, 1), 2), dtype=np.float64)
+    C = np.zeros((M, max(kcap, 1)), dtype=np.complex128) if want_coeffs else None
+    kout = np.zeros(1, dtype=np.int64)
+    if force is not None:
+        force = np.ascontiguousarray(force, dtype=np.int64)
+        nforce = force.size
+    else:
+        nforce = 0
+    fn = {"explicit": lib().oracle_greedy_explicit, "pythag": lib().oracle_greedy_pythag}[mode]
+    st = fn(_ptr(S), N, M, N, float(tol), int(kmax), float(kappa), int(nu_max),
+            _ptr(force) if force is not None else None, nforce,
+            _ptr(E), _ptr(piv), _ptr(err), _ptr(rho), _ptr(nu), _ptr(pick),
+            _ptr(C) if C is not None else None, _ptr(kout))
+    if st < 0:
+        raise RuntimeError("oracle greedy failed: %s" % STATUS.get(st, st))
+    k = int(kout[0])
+    return dict(E=E[:k].copy(), piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(),
+                nu=nu[:k].copy(), pick=pick[:k].copy(),
+                C=(C[:, :k].T.copy() if C is not None else None), k=k, status=STATUS[st])
+
+
+def project(E, S) -> np.ndarray:
+    """C = E^H S as an array of shape (k, M) (row i = coefficients on e_i)."""
+    E = _cmat(E)
+    S = _cmat(S)
+    k, N = E.shape
+    M = S.shape[0]
+    if S.shape[1] != N:
+        raise ValueError("E and S row counts differ")
+    Ct = np.empty((M, max(k, 1)), dtype=np.complex128)
+    lib().oracle_project(_ptr(E), N, k, N, _ptr(S), M, N, _ptr(Ct), max(k, 1))
+    return Ct[:, :k].T.copy()
+
+
+def residual_norms(E, S) -> np.ndarray:
+    """||s_j - E E^H s_j||_2 for every column, computed explicitly."""
+    E = _cmat(E) if len(E) else np.zeros((0, np.asarray(S).shape[1]), dtype=np.complex128)
+    S = _cmat(S)
+    k, N = E.shape
+    M = S.shape[0]
+    out = np.empty(M, dtype=np.float64)
+    lib().oracle_residual_norms(_ptr(E) if k else None, N, k, N, _ptr(S), M, N, _ptr(out))
+    return out
