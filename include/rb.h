@@ -1,0 +1,180 @@
+/*
+ * rb.h -- C ABI of librb.so, an MI355X (gfx950) implementation of the
+ * reduced-basis greedy of Antil, Chen & Field, "A Note on QR-Based Model
+ * Reduction" (arXiv 1805.06124): column-pivoted QR of a dense complex
+ * snapshot matrix S (N rows x M columns) by the RB-greedy (Alg. 3, Sec. 5.2.1,
+ * equivalent to MGS with column pivoting, Alg. 2, by Proposition 5.3).
+ *
+ * Conventions (all entry points)
+ *  - Matrices are column-major: column j of an N x M matrix X with leading
+ *    dimension ldX (>= N) starts at element j*ldX.  Complex numbers are
+ *    interleaved (re, im) pairs: complex128 = two doubles, complex64 = two
+ *    floats.  A row-major torch tensor of shape (M, N) is exactly this layout
+ *    with ld = N.
+ *  - Pointers documented as "device" must point to device memory of the
+ *    current HIP device; "host" pointers to ordinary host memory.  All memory
+ *    passed in is owned by the caller; the library never frees it.  The
+ *    library allocates its own scratch (O(M) words plus, for the greedy, an
+ *    m x M coefficient panel) with hipMalloc and frees it before returning.
+ *  - Work is enqueued on the given stream (NULL = the default stream); every
+ *    call returns after that work has completed, because the greedy takes a
+ *    host decision after every step.
+ *  - Return value: an rb_status code.  Arguments are validated on the host
+ *    before any device work; on error nothing is written.  rb_last_error()
+ *    gives a message for the last failing call on the calling thread.
+ *  - Inner product: <e, s> = e^H s (the paper's real transpose read as the
+ *    conjugate transpose); norms are Euclidean, unweighted.
+ */
+#ifndef RB_H
+#define RB_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rb_status {
+  RB_OK = 0,            /* greedy: stopped because err < tol */
+  RB_KMAX = 1,          /* greedy: stopped at kmax without reaching tol */
+  RB_RANK = 2,          /* greedy: the next pivot lies numerically in the span
+                           of the basis (rank exhausted); err is at rounding
+                           level */
+  RB_EINVAL = -1,       /* bad dimensions, pointers or options */
+  RB_ENOMEM = -2,       /* device allocation failed */
+  RB_EDEVICE = -3,      /* HIP runtime error or no usable device */
+  RB_ENONFINITE = -4    /* S holds a NaN or Inf (or a column norm overflows) */
+} rb_status;
+
+/* Options of the greedy; rb_default_opts() fills the defaults. */
+typedef struct rb_opts {
+  double kappa;     /* Hoffmann's iterated Gram-Schmidt criterion (Sec. 6.1.2):
+                       another pass is made while a pass shrinks ||v|| by at
+                       least the factor kappa.  Default 2. */
+  int32_t nu_max;   /* maximum Gram-Schmidt passes per vector.  Default 4. */
+  int32_t nu_min;   /* minimum passes.  Default 1.  Each pass is one classical
+                       Gram-Schmidt projection in matrix-vector form,
+                       v -= E (E^H v); after nu_max passes the vector is
+                       accepted as it is. */
+  double theta;     /* resolution threshold of the Eq. (6.3) update: when the
+                       largest estimated residual^2 falls below theta times
+                       the largest residual^2 at the last re-anchoring, the
+                       working columns are re-anchored (deflated explicitly).
+                       Default 1e-3. */
+  int32_t anchor_max; /* re-anchor at the latest after this many basis vectors
+                         since the last anchoring (bounds the coefficient
+                         panel, anchor_max x M complex128).  Default 64. */
+  int32_t collect_stats; /* 1: fill rb_stats timings with HIP events. */
+} rb_opts;
+
+/* Per-call statistics (host struct, optional). */
+typedef struct rb_stats {
+  int64_t sweeps;      /* fused sweeps run (one per basis vector after the
+                          first) */
+  int64_t anchors;     /* explicit re-anchorings */
+  int64_t gs_passes;   /* Gram-Schmidt passes over all vectors */
+  double ms_sweep;     /* device time in sweeps (collect_stats = 1) */
+  double ms_gs;        /* device time in orthogonalisation */
+  double ms_anchor;    /* device time in re-anchoring (deflate + norms) */
+  double ms_total;     /* wall time of the call */
+} rb_stats;
+
+void rb_default_opts(rb_opts *opts);
+
+/* Status string for a code, and the message of the calling thread's last
+ * failing call ("" if none). */
+const char *rb_strerror(int status);
+const char *rb_last_error(void);
+
+/*
+ * rb_colnorms_z -- exact squared column norms (the initial residual norms of
+ * Alg. 3, ||s_i||^2).  Each column's sum of squares is accumulated without
+ * rounding error (double-double, error-free products) and rounded to double
+ * once, so every correct implementation returns the same bits.
+ *   S    device, complex128 N x M, ldS >= N           (read)
+ *   nrm  device, double[M]                           (written)
+ * Returns RB_ENONFINITE if any column holds a NaN/Inf or its norm overflows.
+ */
+int rb_colnorms_z(const void *S, int64_t N, int64_t M, int64_t ldS, double *nrm, hipStream_t stream);
+
+/*
+ * rb_sweep_z -- one pivot-search sweep of the greedy (Sec. 6.1.2, Eqs.
+ * (6.1)-(6.3)) fused into a single read of S:
+ *   c_j    = e^H s_j                      for every column j
+ *   acc_j += |c_j|^2                      (running sum of c c*)
+ *   est_j  = nrm_j - acc_j                (estimated squared residual)
+ *   (est_max, J) = max over j with mask_j == 0 of est_j; ties -> lowest j
+ *   S      device, complex128 N x M, ldS >= N  (read)
+ *   e      device, complex128[N], the newest basis vector (read)
+ *   nrm    device, double[M]                   (read)
+ *   acc    device, double[M]                   (read, updated in place)
+ *   mask   device, uint8[M]; nonzero = already pivoted, excluded from the
+ *          argmax (acc is still updated)       (read; may be NULL = none)
+ *   c_out  device, complex128 with stride ldc elements between consecutive
+ *          columns' coefficients: c_j is stored at c_out[j*ldc]; NULL = not
+ *          stored
+ *   est_max, J  host; J = -1 and est_max = -inf if every column is masked.
+ */
+int rb_sweep_z(const void *S, int64_t N, int64_t M, int64_t ldS, const void *e, const double *nrm,
+               double *acc, const uint8_t *mask, void *c_out, int64_t ldc, double *est_max, int64_t *J,
+               hipStream_t stream);
+
+/*
+ * rb_greedy_z -- the RB-greedy (Alg. 3) in FP64 over complex128 S.
+ * Stopping rule (Alg. 3 and Corollary 5.6, tolerance on the unsquared error):
+ * vectors are added while err_k >= tol and k < kmax, where
+ * err_k = max over unpivoted j of ||s_j - E_k E_k^H s_j||_2 (= |R_{k+1,k+1}|).
+ * Pivot k is the argmax of the residual (lowest index on ties); the pivot
+ * column is orthonormalised against the basis by iterated Gram-Schmidt with
+ * Hoffmann's kappa criterion (Sec. 6.1.2).
+ *   S      device, complex128 N x M, ldS >= N.  Read only, unless W == S.
+ *   W      device, complex128 N x M, ldW >= N: working matrix for explicit
+ *          re-anchoring (the residual columns s_j - E E^H s_j are written
+ *          here).  May equal S (S is then overwritten with residuals), or
+ *          NULL: the library allocates it on first use and frees it.
+ *   E      device, complex128 N x kmax, ldE >= N: the basis e_1..e_k (out)
+ *   piv    host int64[kmax]: pivot column indices (0-based) (out)
+ *   err    host double[kmax+1]: err[i] = greedy error with i vectors (out)
+ *   rho    host double[kmax]: ||v|| of pivot i after orthogonalisation,
+ *          i.e. |R_ii| (out)
+ *   nu     host int32[kmax] Gram-Schmidt passes per vector, or NULL (out)
+ *   k_out  host: number of basis vectors k (out)
+ *   opts   NULL = defaults;  stats: NULL or host rb_stats (out)
+ * kmax is clamped to min(N, M).  If max ||s_j|| < tol, k = 0.
+ * Returns RB_OK, RB_KMAX or RB_RANK on success.
+ */
+int rb_greedy_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
+                int64_t ldW, void *E, int64_t ldE, int64_t *piv, double *err, double *rho, int32_t *nu,
+                int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
+ * rb_project_z -- C = E^H S (the coefficients of every snapshot on the
+ * basis; the projection E E^H s of Sec. 4), complex128, FP64 matrix cores.
+ *   E  device, complex128 N x k, ldE >= N     (read)
+ *   S  device, complex128 N x M, ldS >= N     (read)
+ *   C  device, complex128 k x M, ldC >= k     (written)
+ */
+int rb_project_z(const void *E, int64_t N, int64_t k, int64_t ldE, const void *S, int64_t M, int64_t ldS,
+                 void *C, int64_t ldC, hipStream_t stream);
+
+/*
+ * rb_chirp_fill -- the synthetic snapshot family standing in for the paper's
+ * gravitational-wave model (Sec. 6.1.1): column j is the leading-1PN
+ * frequency-domain chirp h(f) = f^(-7/6) exp(-i Psi(f)) with
+ * Psi = -pi/4 + 3/(128 eta v^5) (1 + (3715/756 + 55 eta/9) v^2),
+ * v = (pi Mtot f)^(1/3) (Mtot in seconds = solar masses * GM_sun/c^3),
+ * eta = q/(1+q)^2, on the uniform grid f_n = flo + n (fhi - flo)/(N - 1),
+ * normalised to unit L2 norm.  Evaluated in FP64; dtype 1 rounds the
+ * normalised values to complex64.
+ *   params  device, double[2*M]: (Mtot in solar masses, q) per column (read)
+ *   out     device, complex128 (dtype 0) or complex64 (dtype 1), N x M, ld
+ */
+int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64_t N, int dtype, void *out,
+                  int64_t ld, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RB_H */

@@ -1,0 +1,216 @@
+"""MI355X (gfx950) reduced-basis greedy: Python binding of librb.so.
+
+The arithmetic runs in the HIP library declared by ``include/rb.h``; this
+module only marshals torch tensors (device memory, streams) into the C ABI
+through ctypes.  There is no CPU fallback: ``load()`` raises if the library
+or a GPU is missing.
+
+Layout: a complex snapshot matrix S with N rows and M columns is a torch
+tensor of shape (M, N) (row j = column s_j), complex128 or complex64, on the
+GPU, with unit stride along N (the C side's column-major N x M, ld =
+S.stride(0)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librb.so")
+
+STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE"}
+
+
+class RBError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s failed: %s (%d) %s" % (fn, STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("nu_max", ctypes.c_int32), ("nu_min", ctypes.c_int32),
+                ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("anchors", ctypes.c_int64), ("gs_passes", ctypes.c_int64),
+                ("ms_sweep", ctypes.c_double), ("ms_gs", ctypes.c_double), ("ms_anchor", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "rb_sweep_z", "rb_greedy_z",
+           "rb_project_z", "rb_chirp_fill"]
+
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librb.so and declare the C signatures (no GPU work)."""
+    if not os.path.exists(path):
+        raise RuntimeError("librb.so not built (%s); run paper_1805_06124_amd.build.build()" % path)
+    L = ctypes.CDLL(path)
+    P, I64, D, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32
+    L.rb_default_opts.restype = None
+    L.rb_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.rb_strerror.restype = ctypes.c_char_p
+    L.rb_strerror.argtypes = [ctypes.c_int]
+    L.rb_last_error.restype = ctypes.c_char_p
+    L.rb_last_error.argtypes = []
+    L.rb_colnorms_z.restype = ctypes.c_int
+    L.rb_colnorms_z.argtypes = [P, I64, I64, I64, P, P]
+    L.rb_sweep_z.restype = ctypes.c_int
+    L.rb_sweep_z.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(I64), P]
+    L.rb_greedy_z.restype = ctypes.c_int
+    L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
+                              ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_project_z.restype = ctypes.c_int
+    L.rb_project_z.argtypes = [P, I64, I64, I64, P, I64, I64, P, I64, P]
+    L.rb_chirp_fill.restype = ctypes.c_int
+    L.rb_chirp_fill.argtypes = [P, I64, D, D, I64, ctypes.c_int, P, I64, P]
+    return L
+
+
+def load() -> ctypes.CDLL:
+    """The library, loaded once; requires a GPU (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1805_06124_amd needs a ROCm GPU; none is visible")
+        _lib = load_library()
+    return _lib
+
+
+def _check(fn: str, rc: int, ok=(0,)):
+    if rc not in ok:
+        raise RBError(fn, rc, load().rb_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _mat(S: torch.Tensor, dtype) -> tuple:
+    if not S.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if S.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, S.dtype))
+    if S.dim() != 2 or S.stride(1) != 1 or S.stride(0) < S.shape[1]:
+        raise ValueError("expected a (M, N) tensor with unit stride along N")
+    M, N = S.shape
+    return M, N, S.stride(0)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().rb_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def colnorms(S: torch.Tensor, stream=None) -> torch.Tensor:
+    """Exact ||s_j||^2 for every column (double-double, rounded once)."""
+    M, N, ld = _mat(S, torch.complex128)
+    out = torch.empty(M, dtype=torch.float64, device=S.device)
+    _check("rb_colnorms_z", load().rb_colnorms_z(_ptr(S), N, M, ld, _ptr(out), _stream(stream)))
+    return out
+
+
+def sweep(S: torch.Tensor, e: torch.Tensor, nrm: torch.Tensor, acc: torch.Tensor, mask: torch.Tensor | None = None,
+          c_out: torch.Tensor | None = None, stream=None):
+    """One fused Eq. (6.3) sweep; updates acc in place, writes c_j into c_out
+    (complex128[M]) if given.  Returns (est_max, J)."""
+    M, N, ld = _mat(S, torch.complex128)
+    if e.dtype != torch.complex128 or e.numel() != N or not e.is_contiguous():
+        raise ValueError("e must be a contiguous complex128 vector of length N")
+    for t, n in ((nrm, "nrm"), (acc, "acc")):
+        if t.dtype != torch.float64 or t.numel() != M or not t.is_contiguous():
+            raise ValueError("%s must be contiguous float64[M]" % n)
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != M):
+        raise ValueError("mask must be uint8[M]")
+    if c_out is not None and (c_out.dtype != torch.complex128 or c_out.numel() < M):
+        raise ValueError("c_out must be complex128[M]")
+    est = ctypes.c_double()
+    J = ctypes.c_int64()
+    _check("rb_sweep_z", load().rb_sweep_z(_ptr(S), N, M, ld, _ptr(e), _ptr(nrm), _ptr(acc), _ptr(mask),
+                                           _ptr(c_out), 1, ctypes.byref(est), ctypes.byref(J), _stream(stream)))
+    return est.value, J.value
+
+
+def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None, stream=None, **opts) -> dict:
+    """RB-greedy (Alg. 3) over complex128 S.  W: optional (M, N) working matrix
+    for re-anchoring (may be S itself: S is then overwritten).  Returns dict
+    with E (k, N) complex128 on the GPU, piv, err, rho, nu (numpy), k,
+    status and stats."""
+    import numpy as np
+    M, N, ld = _mat(S, torch.complex128)
+    kcap = max(0, min(int(kmax), N, M))
+    E = torch.empty((max(kcap, 1), N), dtype=torch.complex128, device=S.device)
+    piv = np.zeros(max(kcap, 1), dtype=np.int64)
+    err = np.zeros(kcap + 1, dtype=np.float64)
+    rho = np.zeros(max(kcap, 1), dtype=np.float64)
+    nu = np.zeros(max(kcap, 1), dtype=np.int32)
+    kout = ctypes.c_int64()
+    o = default_opts(**opts)
+    st = Stats()
+    if W is not None:
+        Mw, Nw, ldW = _mat(W, torch.complex128)
+        if (Mw, Nw) != (M, N):
+            raise ValueError("W must have the shape of S")
+    else:
+        ldW = N
+    rc = load().rb_greedy_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N,
+                            piv.ctypes.data_as(ctypes.c_void_p), err.ctypes.data_as(ctypes.c_void_p),
+                            rho.ctypes.data_as(ctypes.c_void_p), nu.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
+    _check("rb_greedy_z", rc, ok=(0, 1, 2))
+    k = kout.value
+    return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
+                status=STATUS[rc], stats=st.as_dict())
+
+
+def project(E: torch.Tensor, S: torch.Tensor, stream=None) -> torch.Tensor:
+    """C = E^H S on FP64 matrix cores.  E: (k, N), S: (M, N) complex128.
+    Returns a (M, k) tensor whose row j holds the coefficients of s_j."""
+    k, N, ldE = _mat(E, torch.complex128)
+    M, N2, ldS = _mat(S, torch.complex128)
+    if N != N2:
+        raise ValueError("E and S row counts differ")
+    C = torch.empty((M, k), dtype=torch.complex128, device=S.device)
+    _check("rb_project_z", load().rb_project_z(_ptr(E), N, k, ldE, _ptr(S), M, ldS, _ptr(C), k, _stream(stream)))
+    return C
+
+
+def chirp_fill(params: torch.Tensor, N: int, flo: float, fhi: float, dtype=torch.complex128,
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Unit-norm chirp snapshots on the GPU; params (M, 2) float64 (Mtot in
+    solar masses, q) on the GPU.  Returns (M, N) complex128 or complex64."""
+    if not params.is_cuda or params.dtype != torch.float64 or not params.is_contiguous():
+        raise ValueError("params must be a contiguous float64 GPU tensor of shape (M, 2)")
+    M = params.numel() // 2
+    code = {torch.complex128: 0, torch.complex64: 1}[dtype]
+    if out is None:
+        out = torch.empty((M, N), dtype=dtype, device=params.device)
+    Mo, No, ld = _mat(out, dtype)
+    if (Mo, No) != (M, N):
+        raise ValueError("out has the wrong shape")
+    _check("rb_chirp_fill", load().rb_chirp_fill(_ptr(params), M, float(flo), float(fhi), int(N), code, _ptr(out),
+                                                 ld, _stream(stream)))
+    return out

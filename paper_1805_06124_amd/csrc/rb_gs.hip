@@ -1,0 +1,142 @@
+// Orthogonalisation of a pivot column against the basis (Sec. 6.1.2): the
+// building blocks of one Gram-Schmidt pass in matrix-vector form,
+//   G = E^H V   (k x nv),   V -= E G,   ||v_r||^2,
+// plus the final scaling e = v / ||v||.  E holds k basis vectors of length N
+// (column-major, ldE); V holds nv vectors (ldV).  These kernels touch
+// O(k N) data per pass, far below one sweep of S.
+#include "rb_internal.h"
+
+namespace rb {
+
+namespace {
+
+constexpr int kGsThreads = 256;
+
+// One workgroup per basis vector i: G[i + r*k] = e_i^H v_r for r < nv.
+__global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restrict__ E, int64_t ldE, int64_t k,
+                                                        const double2* __restrict__ V, int64_t ldV, int64_t nv,
+                                                        int64_t N, double2* __restrict__ G) {
+  const int64_t i = blockIdx.x;
+  const double2* e = E + i * ldE;
+  __shared__ double sre[kGsThreads / 64], sim[kGsThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t r = 0; r < nv; ++r) {
+    const double2* v = V + r * ldV;
+    double re = 0.0, im = 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += kGsThreads) {
+      double2 a = e[n], b = v[n];
+      re += a.x * b.x + a.y * b.y;
+      im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+      sre[wave] = re;
+      sim[wave] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tr = 0.0, ti = 0.0;
+      for (int w = 0; w < kGsThreads / 64; ++w) {
+        tr += sre[w];
+        ti += sim[w];
+      }
+      G[i + r * k] = make_double2(tr, ti);
+    }
+    __syncthreads();
+  }
+}
+
+// V[n + r*ldV] -= sum_i E[n + i*ldE] G[i + r*k]; one thread per row n.
+__global__ __launch_bounds__(kGsThreads) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
+                                                           const double2* __restrict__ G, double2* __restrict__ V,
+                                                           int64_t ldV, int64_t nv, int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+  if (n >= N) return;
+  constexpr int kMaxNv = 8;
+  double re[kMaxNv], im[kMaxNv];
+#pragma unroll
+  for (int r = 0; r < kMaxNv; ++r) re[r] = im[r] = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    double2 a = E[n + i * ldE];
+#pragma unroll
+    for (int r = 0; r < kMaxNv; ++r) {
+      if (r < nv) {
+        double2 g = G[i + r * k];
+        re[r] += a.x * g.x - a.y * g.y;
+        im[r] += a.x * g.y + a.y * g.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxNv; ++r) {
+    if (r < nv) {
+      double2 v = V[n + r * ldV];
+      V[n + r * ldV] = make_double2(v.x - re[r], v.y - im[r]);
+    }
+  }
+}
+
+// out[r] = ||v_r||^2, accumulated exactly (double-double) and rounded once;
+// one workgroup per vector.
+__global__ __launch_bounds__(1024) void k_sqnorms_small(const double2* __restrict__ V, int64_t ldV, int64_t N,
+                                                        double* __restrict__ out) {
+  const double2* v = V + (int64_t)blockIdx.x * ldV;
+  dd s = {0.0, 0.0};
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
+    double2 a = v[n];
+    dd_add_sq(s, a.x);
+    dd_add_sq(s, a.y);
+  }
+  s = wave_dd_sum(s);
+  __shared__ dd sh[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd t = sh[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) t = dd_add(t, sh[w]);
+    out[blockIdx.x] = t.hi + t.lo;
+  }
+}
+
+// out = v / sqrt(sq[0])
+__global__ __launch_bounds__(kGsThreads) void k_scale_into(const double2* __restrict__ v, int64_t N,
+                                                           const double* __restrict__ sq, double2* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+  if (n >= N) return;
+  const double r = sqrt(sq[0]);
+  double2 a = v[n];
+  out[n] = make_double2(a.x / r, a.y / r);
+}
+
+}  // namespace
+
+hipError_t launch_gemv_ch(const double2* E, int64_t ldE, int64_t k, const double2* V, int64_t ldV, int64_t nv,
+                          int64_t N, double2* G, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kGsThreads), 0, s, E, ldE, k, V, ldV, nv, N, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_n_sub(const double2* E, int64_t ldE, int64_t k, const double2* G, double2* V, int64_t ldV,
+                             int64_t nv, int64_t N, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  if (nv > 8) return hipErrorInvalidValue;
+  int64_t grid = (N + kGsThreads - 1) / kGsThreads;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)grid), dim3(kGsThreads), 0, s, E, ldE, k, G, V, ldV, nv, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64_t N, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sqnorms_small, dim3((unsigned)nv), dim3(1024), 0, s, V, ldV, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_into(const double2* v, int64_t N, const double* sq, double2* out, hipStream_t s) {
+  int64_t grid = (N + kGsThreads - 1) / kGsThreads;
+  hipLaunchKernelGGL(k_scale_into, dim3((unsigned)grid), dim3(kGsThreads), 0, s, v, N, sq, out);
+  return hipGetLastError();
+}
+
+}  // namespace rb

@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP translation units of librb.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rb.h"
+
+namespace rb {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- device --
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// Streaming 16-byte load that bypasses cache retention (S is read once per
+// sweep; keeping it out of L2/MALL leaves room for the basis vector).
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(v.x, v.y);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Error-free transformations (Knuth two-sum; fma product) for the exact
+// squared norms.  Contraction is switched off in each of them: fusing the
+// product v*v into the following sum would break the two-sum identity.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ void dd_add_sq(dd& x, double v) {
+#pragma clang fp contract(off)
+  double p = v * v;
+  double pe = __builtin_fma(v, v, -p);
+  double s, e;
+  two_sum(x.hi, p, s, e);
+  x.hi = s;
+  x.lo += e + pe;
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+#pragma clang fp contract(off)
+  double s, e;
+  two_sum(a.hi, b.hi, s, e);
+  e += a.lo + b.lo;
+  dd r;
+  r.hi = s + e;  // fast two-sum renormalisation
+  r.lo = e - (r.hi - s);
+  return r;
+}
+__device__ __forceinline__ dd wave_dd_sum(dd x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dd y;
+    y.hi = __shfl_xor(x.hi, o, kWave);
+    y.lo = __shfl_xor(x.lo, o, kWave);
+    x = dd_add(x, y);
+  }
+  return x;
+}
+
+// (value, index) argmax with ties to the lowest index.  The combination is
+// associative and commutative, so every reduction order gives the same
+// result.
+struct vi {
+  double v;
+  int64_t i;
+};
+// An index < 0 marks "no candidate".
+__device__ __forceinline__ vi vi_max(vi a, vi b) {
+  if (a.i < 0) return b;
+  if (b.i < 0) return a;
+  if (b.v > a.v) return b;
+  if (b.v < a.v) return a;
+  return (b.i < a.i) ? b : a;
+}
+__device__ __forceinline__ vi wave_vi_max(vi x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    vi y;
+    y.v = __shfl_xor(x.v, o, kWave);
+    y.i = __shfl_xor(x.i, o, kWave);
+    x = vi_max(x, y);
+  }
+  return x;
+}
+
+// ------------------------------------------------------------------ host --
+
+// Device argmax result record.
+struct ArgMax {
+  double v;
+  int64_t i;
+};
+
+// launchers (each defined in the translation unit that holds the kernel)
+hipError_t launch_colnorms_z(const double2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
+                             hipStream_t s);
+hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* e,
+                          const double* nrm, double* acc, const uint8_t* mask, double2* c_out, int64_t ldc,
+                          ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
+hipError_t launch_est_argmax(const double* nrm, const double* acc, const uint8_t* mask, int64_t M,
+                             ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
+int64_t sweep_partials_needed(int64_t M);
+
+// Gram-Schmidt building blocks over the basis E (N x k, ldE) and nv vectors
+// V (N x nv, ldV):  G = E^H V ;  V -= E G ;  norms.
+hipError_t launch_gemv_ch(const double2* E, int64_t ldE, int64_t k, const double2* V, int64_t ldV,
+                          int64_t nv, int64_t N, double2* G, hipStream_t s);
+hipError_t launch_gemv_n_sub(const double2* E, int64_t ldE, int64_t k, const double2* G, double2* V,
+                             int64_t ldV, int64_t nv, int64_t N, hipStream_t s);
+hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64_t N, double* out,
+                                hipStream_t s);
+hipError_t launch_scale_into(const double2* v, int64_t N, const double* sq, double2* out, hipStream_t s);
+
+// Re-anchoring: W[:, j] = X[:, j] - sum_{i<m} E[:, i] C(i, j) with
+// C(i, j) = C[i*cI + j*cJ]  (X may equal W)
+hipError_t launch_deflate_z(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
+                            const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                            hipStream_t s);
+// C = E^H S on FP64 matrix cores
+hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
+                            int64_t ldS, double2* C, int64_t ldC, hipStream_t s);
+
+hipError_t launch_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64_t N, int dtype,
+                             void* out, int64_t ld, hipStream_t s);
+
+}  // namespace rb

@@ -1,0 +1,107 @@
+"""The C ABI of librb.so: it loads, exports every entry point include/rb.h
+declares, and validates arguments on the host before any device work.
+CPU only (no call here reaches a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1805_06124_amd as rbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rb.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rb_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(rbm.LIB_PATH):
+        pytest.skip("librb.so not built")
+    return rbm.load_library()
+
+
+def test_header_declares_expected_entry_points():
+    d = _declared()
+    for name in ("rb_greedy_z", "rb_sweep_z", "rb_colnorms_z", "rb_project_z", "rb_chirp_fill",
+                 "rb_default_opts", "rb_strerror", "rb_last_error"):
+        assert name in d
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(rbm.EXPORTS) <= set(_declared())
+
+
+def test_default_opts_and_strerror(L):
+    o = rbm.Opts()
+    L.rb_default_opts(ctypes.byref(o))
+    assert o.kappa == 2.0 and o.nu_max == 4 and o.nu_min == 1 and o.anchor_max == 64
+    assert 0 < o.theta < 1
+    assert b"invalid" in L.rb_strerror(-1)
+    assert b"kmax" in L.rb_strerror(1)
+
+
+def _greedy_args(N=10, M=10, ldS=10, kmax=3, tol=1e-10, S=1, E=1, ldE=10, piv=True):
+    import numpy as np
+    P = ctypes.c_void_p
+    piv_a = np.zeros(4, dtype=np.int64)
+    err = np.zeros(5)
+    rho = np.zeros(4)
+    k = ctypes.c_int64(-7)
+    return [P(S) if S else None, N, M, ldS, tol, kmax, None, 0, P(E) if E else None, ldE,
+            piv_a.ctypes.data_as(P) if piv else None, err.ctypes.data_as(P), rho.ctypes.data_as(P), None,
+            ctypes.byref(k), None, None, None], k
+
+
+@pytest.mark.parametrize("bad", [dict(N=0), dict(M=-1), dict(ldS=5), dict(kmax=-1), dict(tol=-1.0),
+                                 dict(tol=float("nan")), dict(S=0), dict(E=0), dict(ldE=3), dict(piv=False)])
+def test_greedy_rejects_bad_arguments_on_host(L, bad):
+    args, k = _greedy_args(**bad)
+    assert L.rb_greedy_z(*args) == -1
+    assert k.value == -7  # nothing written
+    assert L.rb_last_error()
+
+
+def test_other_entry_points_reject_bad_arguments(L):
+    P = ctypes.c_void_p
+    d = ctypes.c_double()
+    j = ctypes.c_int64()
+    assert L.rb_colnorms_z(None, 4, 4, 4, P(1), None) == -1
+    assert L.rb_colnorms_z(P(1), 4, 4, 3, P(1), None) == -1
+    assert L.rb_sweep_z(P(1), 4, 4, 4, None, P(1), P(1), None, None, 1, ctypes.byref(d), ctypes.byref(j), None) == -1
+    assert L.rb_project_z(P(1), 4, 2, 4, P(1), 4, 4, P(1), 1, None) == -1  # ldC < k
+    assert L.rb_chirp_fill(P(1), 4, 0.0, 10.0, 8, 0, P(1), 8, None) == -1  # flo must be > 0
+    assert L.rb_chirp_fill(P(1), 4, 20.0, 10.0, 8, 0, P(1), 8, None) == -1  # fhi < flo
+    assert L.rb_chirp_fill(P(1), 4, 20.0, 30.0, 8, 2, P(1), 8, None) == -1  # dtype
+
+
+def test_bad_options_rejected(L):
+    o = rbm.Opts()
+    L.rb_default_opts(ctypes.byref(o))
+    o.kappa = 1.0
+    args, k = _greedy_args()
+    args[15] = ctypes.byref(o)
+    assert L.rb_greedy_z(*args) == -1
+
+
+def test_product_package_does_not_import_oracle():
+    import ast
+    pkg = os.path.join(ROOT, "paper_1805_06124_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                tree = ast.parse(open(os.path.join(dirpath, f)).read())
+                for node in ast.walk(tree):
+                    if isinstance(node, ast.Import):
+                        assert all(not a.name.startswith("oracle") for a in node.names)
+                    if isinstance(node, ast.ImportFrom):
+                        assert not (node.module or "").startswith("oracle")
+            if f.endswith((".hip", ".h", ".cpp")):
+                assert "oracle" not in open(os.path.join(dirpath, f)).read().lower()
