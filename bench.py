@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--workload", default="chirp_10k_409600_c128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slice", type=int, default=51200)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
