@@ -65,20 +65,37 @@ typedef struct rb_opts {
                        Default 1e-3. */
   int32_t anchor_max; /* re-anchor at the latest after this many basis vectors
                          since the last anchoring (bounds the coefficient
-                         panel, anchor_max x M complex128).  Default 64. */
+                         panel, anchor_max x M complex128).  Default 128. */
   int32_t collect_stats; /* 1: fill rb_stats timings with HIP events. */
+  /* mixed precision (rb_greedy_c) only: */
+  double theta32;     /* re-anchor when the largest estimated residual^2 of
+                         the complex64 sweep falls below theta32 times its
+                         last anchored scale.  Default 1e-4. */
+  int32_t regen_chunk; /* columns regenerated in FP64 per chunk during an
+                          exact re-anchoring (scratch: regen_chunk x N
+                          complex128 plus kmax x regen_chunk complex128).
+                          Default 32768. */
+  int32_t certify;    /* 1: before returning converged, recompute every
+                         column's residual exactly in FP64 from regenerated
+                         columns and continue if it is still >= tol.
+                         Default 1. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */
 typedef struct rb_stats {
   int64_t sweeps;      /* fused sweeps run (one per basis vector after the
                           first) */
-  int64_t anchors;     /* explicit re-anchorings */
+  int64_t anchors;     /* explicit re-anchorings (all kinds) */
   int64_t gs_passes;   /* Gram-Schmidt passes over all vectors */
   double ms_sweep;     /* device time in sweeps (collect_stats = 1) */
-  double ms_gs;        /* device time in orthogonalisation */
-  double ms_anchor;    /* device time in re-anchoring (deflate + norms) */
+  double ms_gs;        /* device time in orthogonalisation (and, mixed
+                          precision, candidate confirmation) */
+  double ms_anchor;    /* device time in re-anchoring */
   double ms_total;     /* wall time of the call */
+  int64_t regen_anchors; /* mixed: re-anchorings from regenerated FP64
+                            columns (the others deflate the stored columns) */
+  int64_t misses;      /* mixed: steps whose confirmed pivot was not the
+                          sweep's top candidate */
 } rb_stats;
 
 void rb_default_opts(rb_opts *opts);
@@ -122,6 +139,19 @@ int rb_sweep_z(const void *S, int64_t N, int64_t M, int64_t ldS, const void *e, 
                hipStream_t stream);
 
 /*
+ * rb_sweep_c -- the mixed-precision sweep of rb_greedy_c: as rb_sweep_z but
+ * over complex64 columns with a complex64 copy of the basis vector; products
+ * and row-tile sums in FP32 (tiles of 512 rows per lane group), FP64 across
+ * tiles; acc, est and c_out FP64.  Returns the 8 largest (est, index) pairs
+ * over unmasked columns in est_top[0..8), J_top[0..8) (host), descending,
+ * ties to the lower index; unused slots have J_top = -1.
+ *   S32  device, complex64 N x M, ldS >= N;  e32 device, complex64[N]
+ */
+int rb_sweep_c(const void *S32, int64_t N, int64_t M, int64_t ldS, const void *e32, const double *nrm,
+               double *acc, const uint8_t *mask, void *c_out, int64_t ldc, double *est_top, int64_t *J_top,
+               hipStream_t stream);
+
+/*
  * rb_greedy_z -- the RB-greedy (Alg. 3) in FP64 over complex128 S.
  * Stopping rule (Alg. 3 and Corollary 5.6, tolerance on the unsquared error):
  * vectors are added while err_k >= tol and k < kmax, where
@@ -148,6 +178,57 @@ int rb_sweep_z(const void *S, int64_t N, int64_t M, int64_t ldS, const void *e, 
 int rb_greedy_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
                 int64_t ldW, void *E, int64_t ldE, int64_t *piv, double *err, double *rho, int32_t *nu,
                 int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
+ * rb_regen_fn -- regenerates snapshot columns in FP64 from their parameters
+ * (the paper's model interface: S is filled by calls to a model, Sec. 6.1.1).
+ *   ctx   caller context
+ *   cols  device int64[n]: column indices to regenerate
+ *   out   device complex128 N x n, leading dimension ldo (written); column
+ *         r receives snapshot cols[r]
+ * Must enqueue on `stream` and return 0 on success (nonzero aborts the
+ * greedy with RB_EDEVICE).
+ */
+typedef int (*rb_regen_fn)(void *ctx, const int64_t *cols, int64_t n, void *out, int64_t ldo,
+                           hipStream_t stream);
+
+/* Context of the built-in regenerator rb_chirp_regen: the chirp family of
+ * rb_chirp_fill with parameters params (device, 2*M doubles), band
+ * [flo, fhi] and N rows. */
+typedef struct rb_chirp_ctx {
+  const double *params;
+  double flo, fhi;
+  int64_t N;
+} rb_chirp_ctx;
+
+/* rb_regen_fn for the chirp family (ctx is a rb_chirp_ctx*). */
+int rb_chirp_regen(void *ctx, const int64_t *cols, int64_t n, void *out, int64_t ldo, hipStream_t stream);
+
+/*
+ * rb_greedy_c -- the RB-greedy with complex64 snapshot storage (mixed
+ * precision).  The pivot search sweeps the complex64 columns with an FP32
+ * copy of the newest basis vector (FP32 products, FP32 sums per row tile,
+ * FP64 across tiles); acc, est and the coefficients are FP64.  The sweep
+ * nominates its 8 best candidates; each is regenerated in FP64 by `regen`
+ * and orthogonalised against the FP64 basis (iterated Gram-Schmidt, kappa
+ * criterion); the pivot is the candidate with the largest exact FP64
+ * residual rho, and err_k is that rho (Corollary 5.6: the greedy error is
+ * the next pivot's residual).  When the complex64 estimate loses
+ * resolution the stored columns are re-anchored to their residuals, either
+ * by deflating the stored values (while the rounding this leaves stays
+ * below a tenth of tol, or will be reset by a later exact re-anchoring) or
+ * exactly, from columns regenerated in FP64.  With opts->certify the final
+ * error is checked over all columns from regenerated FP64 columns.
+ *   S32    device, complex64 N x M, ldS >= N (read only unless W32 == S32)
+ *   regen, regen_ctx   column regenerator (required)
+ *   W32    device, complex64 N x M working matrix (ldW), may equal S32, or
+ *          NULL (allocated on first use)
+ *   E, piv, err, rho, nu, k_out, opts, stats: as rb_greedy_z (E is FP64)
+ */
+int rb_greedy_c(const void *S32, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                rb_regen_fn regen, void *regen_ctx, void *W32, int64_t ldW, void *E, int64_t ldE,
+                int64_t *piv, double *err, double *rho, int32_t *nu, int64_t *k_out, const rb_opts *opts,
+                rb_stats *stats, hipStream_t stream);
 
 /*
  * rb_project_z -- C = E^H S (the coefficients of every snapshot on the

@@ -31,20 +31,26 @@ class RBError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("nu_max", ctypes.c_int32), ("nu_min", ctypes.c_int32),
-                ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32)]
+                ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
+                ("theta32", ctypes.c_double), ("regen_chunk", ctypes.c_int32), ("certify", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("anchors", ctypes.c_int64), ("gs_passes", ctypes.c_int64),
                 ("ms_sweep", ctypes.c_double), ("ms_gs", ctypes.c_double), ("ms_anchor", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("regen_anchors", ctypes.c_int64), ("misses", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ChirpCtx(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("flo", ctypes.c_double), ("fhi", ctypes.c_double),
+                ("N", ctypes.c_int64)]
+
+
 EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "rb_sweep_z", "rb_greedy_z",
-           "rb_project_z", "rb_chirp_fill"]
+           "rb_sweep_c", "rb_greedy_c", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill"]
 
 _lib = None
 
@@ -72,6 +78,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_greedy_z.restype = ctypes.c_int
     L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_sweep_c.restype = ctypes.c_int
+    L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
+    L.rb_greedy_c.restype = ctypes.c_int
+    L.rb_greedy_c.argtypes = [P, I64, I64, I64, D, I64, P, P, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
+                              ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_chirp_regen.restype = ctypes.c_int
+    L.rb_chirp_regen.argtypes = [P, P, I64, P, I64, P]
     L.rb_project_z.restype = ctypes.c_int
     L.rb_project_z.argtypes = [P, I64, I64, I64, P, I64, I64, P, I64, P]
     L.rb_chirp_fill.restype = ctypes.c_int
@@ -181,6 +194,69 @@ def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None
                             rho.ctypes.data_as(ctypes.c_void_p), nu.ctypes.data_as(ctypes.c_void_p),
                             ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
     _check("rb_greedy_z", rc, ok=(0, 1, 2))
+    k = kout.value
+    return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
+                status=STATUS[rc], stats=st.as_dict())
+
+
+def sweep_c(S32: torch.Tensor, e32: torch.Tensor, nrm: torch.Tensor, acc: torch.Tensor,
+            mask: torch.Tensor | None = None, c_out: torch.Tensor | None = None, stream=None):
+    """One mixed-precision sweep (complex64 S32, complex64 e32); updates acc in
+    place, writes c_j (complex128) into c_out if given.  Returns the 8 best
+    (est, J) as two numpy arrays (J = -1 for unused slots)."""
+    import numpy as np
+    M, N, ld = _mat(S32, torch.complex64)
+    if e32.dtype != torch.complex64 or e32.numel() != N or not e32.is_contiguous():
+        raise ValueError("e32 must be a contiguous complex64 vector of length N")
+    for t, n in ((nrm, "nrm"), (acc, "acc")):
+        if t.dtype != torch.float64 or t.numel() != M or not t.is_contiguous():
+            raise ValueError("%s must be contiguous float64[M]" % n)
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != M):
+        raise ValueError("mask must be uint8[M]")
+    if c_out is not None and (c_out.dtype != torch.complex128 or c_out.numel() < M):
+        raise ValueError("c_out must be complex128[M]")
+    est = np.zeros(8)
+    J = np.zeros(8, dtype=np.int64)
+    _check("rb_sweep_c", load().rb_sweep_c(_ptr(S32), N, M, ld, _ptr(e32), _ptr(nrm), _ptr(acc), _ptr(mask),
+                                           _ptr(c_out), 1, est.ctypes.data_as(ctypes.c_void_p),
+                                           J.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return est, J
+
+
+def greedy_c(S32: torch.Tensor, tol: float, kmax: int, params: torch.Tensor, flo: float, fhi: float,
+             W: torch.Tensor | None = None, stream=None, **opts) -> dict:
+    """Mixed-precision RB-greedy over complex64 S32 (basis in FP64).  Columns
+    are regenerated in FP64 by the built-in chirp regenerator from `params`
+    ((M, 2) float64 on the GPU: Mtot in solar masses, q) on [flo, fhi].
+    W: optional (M, N) complex64 working matrix (may be S32 itself)."""
+    import numpy as np
+    M, N, ld = _mat(S32, torch.complex64)
+    if not params.is_cuda or params.dtype != torch.float64 or params.numel() != 2 * M or not params.is_contiguous():
+        raise ValueError("params must be a contiguous float64 GPU tensor of shape (M, 2)")
+    kcap = max(0, min(int(kmax), N, M))
+    E = torch.empty((max(kcap, 1), N), dtype=torch.complex128, device=S32.device)
+    piv = np.zeros(max(kcap, 1), dtype=np.int64)
+    err = np.zeros(kcap + 1, dtype=np.float64)
+    rho = np.zeros(max(kcap, 1), dtype=np.float64)
+    nu = np.zeros(max(kcap, 1), dtype=np.int32)
+    kout = ctypes.c_int64()
+    o = default_opts(**opts)
+    st = Stats()
+    if W is not None:
+        Mw, Nw, ldW = _mat(W, torch.complex64)
+        if (Mw, Nw) != (M, N):
+            raise ValueError("W must have the shape of S32")
+    else:
+        ldW = N
+    L = load()
+    ctx = ChirpCtx(params.data_ptr(), float(flo), float(fhi), N)
+    fn = ctypes.cast(L.rb_chirp_regen, ctypes.c_void_p)
+    rc = L.rb_greedy_c(_ptr(S32), N, M, ld, float(tol), int(kmax), fn, ctypes.cast(ctypes.pointer(ctx), ctypes.c_void_p),
+                       _ptr(W), ldW, _ptr(E), N, piv.ctypes.data_as(ctypes.c_void_p),
+                       err.ctypes.data_as(ctypes.c_void_p), rho.ctypes.data_as(ctypes.c_void_p),
+                       nu.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st),
+                       _stream(stream))
+    _check("rb_greedy_c", rc, ok=(0, 1, 2))
     k = kout.value
     return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
                 status=STATUS[rc], stats=st.as_dict())

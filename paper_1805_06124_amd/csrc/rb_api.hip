@@ -23,13 +23,16 @@
 #include <cstring>
 #include <string>
 
-#include "rb_internal.h"
+#include "rb_host.h"
 
 using namespace rb;
 
-namespace {
+namespace rb {
 
-thread_local std::string g_last_error;
+std::string& last_error() {
+  static thread_local std::string msg;
+  return msg;
+}
 
 int set_error(int code, const char* fmt, ...) {
   char buf[512];
@@ -37,81 +40,11 @@ int set_error(int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_last_error = buf;
+  last_error() = buf;
   return code;
 }
 
-#define RB_HIP(expr)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess) return set_error(RB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-// Device buffer owned by one call.
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
-  template <class T>
-  T* as() const {
-    return reinterpret_cast<T*>(p);
-  }
-};
-
-// Pinned host buffer owned by one call.
-struct HostBuf {
-  void* p = nullptr;
-  ~HostBuf() {
-    if (p) (void)hipHostFree(p);
-  }
-  hipError_t alloc(size_t bytes) { return hipHostMalloc(&p, bytes, hipHostMallocDefault); }
-  template <class T>
-  T* as() const {
-    return reinterpret_cast<T*>(p);
-  }
-};
-
-#define RB_ALLOC(buf, bytes)                                                                              \
-  do {                                                                                                    \
-    if ((buf).alloc(bytes) != hipSuccess) {                                                               \
-      (void)hipGetLastError();                                                                            \
-      return set_error(RB_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes));              \
-    }                                                                                                     \
-  } while (0)
-
-struct EventTimer {
-  bool on = false;
-  hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t s = nullptr;
-  double* sink = nullptr;
-  EventTimer(bool enable, hipStream_t st) : on(enable), s(st) {
-    if (on) {
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) on = false;
-    }
-  }
-  ~EventTimer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-  void start() {
-    if (on) (void)hipEventRecord(a, s);
-  }
-  // stop and accumulate (synchronises on the stop event)
-  void stop(double* acc) {
-    if (!on) return;
-    (void)hipEventRecord(b, s);
-    (void)hipEventSynchronize(b);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, a, b);
-    *acc += ms;
-  }
-};
-
-bool valid_ld(int64_t N, int64_t ld) { return ld >= N && ld > 0; }
-
-}  // namespace
+}  // namespace rb
 
 extern "C" {
 
@@ -121,8 +54,11 @@ void rb_default_opts(rb_opts* o) {
   o->nu_max = 4;
   o->nu_min = 1;
   o->theta = 1e-3;
-  o->anchor_max = 64;
+  o->anchor_max = 128;
   o->collect_stats = 0;
+  o->theta32 = 1e-4;
+  o->regen_chunk = 32768;
+  o->certify = 1;
 }
 
 const char* rb_strerror(int status) {
@@ -138,10 +74,10 @@ const char* rb_strerror(int status) {
   }
 }
 
-const char* rb_last_error(void) { return g_last_error.c_str(); }
+const char* rb_last_error(void) { return last_error().c_str(); }
 
 int rb_colnorms_z(const void* S, int64_t N, int64_t M, int64_t ldS, double* nrm, hipStream_t stream) {
-  g_last_error.clear();
+  last_error().clear();
   if (!S || !nrm || N <= 0 || M <= 0 || !valid_ld(N, ldS)) return set_error(RB_EINVAL, "rb_colnorms_z: bad arguments");
   DevBuf bad;
   RB_ALLOC(bad, sizeof(int));
@@ -156,7 +92,7 @@ int rb_colnorms_z(const void* S, int64_t N, int64_t M, int64_t ldS, double* nrm,
 
 int rb_sweep_z(const void* S, int64_t N, int64_t M, int64_t ldS, const void* e, const double* nrm, double* acc,
                const uint8_t* mask, void* c_out, int64_t ldc, double* est_max, int64_t* J, hipStream_t stream) {
-  g_last_error.clear();
+  last_error().clear();
   if (!S || !e || !nrm || !acc || !est_max || !J || N <= 0 || M <= 0 || !valid_ld(N, ldS) || (c_out && ldc <= 0))
     return set_error(RB_EINVAL, "rb_sweep_z: bad arguments");
   const int64_t np = sweep_partials_needed(M);
@@ -175,7 +111,7 @@ int rb_sweep_z(const void* S, int64_t N, int64_t M, int64_t ldS, const void* e, 
 
 int rb_project_z(const void* E, int64_t N, int64_t k, int64_t ldE, const void* S, int64_t M, int64_t ldS, void* C,
                  int64_t ldC, hipStream_t stream) {
-  g_last_error.clear();
+  last_error().clear();
   if (!E || !S || !C || N <= 0 || k <= 0 || M <= 0 || !valid_ld(N, ldE) || !valid_ld(N, ldS) || ldC < k)
     return set_error(RB_EINVAL, "rb_project_z: bad arguments");
   if ((k + 63) / 64 > 65535) return set_error(RB_EINVAL, "rb_project_z: k too large");
@@ -187,11 +123,11 @@ int rb_project_z(const void* E, int64_t N, int64_t k, int64_t ldE, const void* S
 
 int rb_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64_t N, int dtype, void* out, int64_t ld,
                   hipStream_t stream) {
-  g_last_error.clear();
+  last_error().clear();
   if (!params || !out || M <= 0 || N <= 0 || !valid_ld(N, ld) || (dtype != 0 && dtype != 1) || !(flo > 0.0) ||
       !(fhi >= flo) || M > 0x7fffffffLL)
     return set_error(RB_EINVAL, "rb_chirp_fill: bad arguments");
-  RB_HIP(launch_chirp_fill(params, M, flo, fhi, N, dtype, out, ld, stream));
+  RB_HIP(launch_chirp_fill(params, nullptr, M, flo, fhi, N, dtype, out, ld, stream));
   RB_HIP(hipStreamSynchronize(stream));
   return RB_OK;
 }
@@ -199,7 +135,7 @@ int rb_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64
 int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W_, int64_t ldW,
                 void* E_, int64_t ldE, int64_t* piv, double* err, double* rho, int32_t* nu, int64_t* k_out,
                 const rb_opts* opts_in, rb_stats* stats, hipStream_t stream) {
-  g_last_error.clear();
+  last_error().clear();
   const auto t_begin = std::chrono::steady_clock::now();
   rb_opts o;
   rb_default_opts(&o);
@@ -291,15 +227,10 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
       W = d_Wown.as<double2>();
       ldWk = N;
     }
-    if (m > 0) {
-      RB_HIP(launch_deflate_z(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, stream));
-    } else if (X != W) {
-      RB_HIP(hipMemcpy2DAsync(W, sizeof(double2) * ldWk, X, sizeof(double2) * ldX, sizeof(double2) * N, M,
-                              hipMemcpyDeviceToDevice, stream));
-    }
+    // W = X - E[:, a:a+m] C_panel and exact norms of the new columns
+    RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(), stream));
     X = W;
     ldX = ldWk;
-    RB_HIP(launch_colnorms_z(X, N, M, ldX, nrm, d_bad.as<int>(), stream));
     RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
     RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));

@@ -35,13 +35,16 @@ __device__ __forceinline__ double2 chirp_value(const ChirpCol p, double flo, dou
   return make_double2(amp * c, -(amp * s));
 }
 
+// Output column j is the snapshot of parameter set pj = cols ? cols[j] : j.
 template <int kDtype>
-__global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restrict__ params, int64_t M, double flo,
-                                                         double fhi, int64_t N, void* __restrict__ out, int64_t ld) {
+__global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restrict__ params,
+                                                         const int64_t* __restrict__ cols, double flo, double fhi,
+                                                         int64_t N, void* __restrict__ out, int64_t ld) {
   const int64_t j = blockIdx.x;
+  const int64_t pj = cols ? cols[j] : j;
   ChirpCol p;
-  p.Mt = params[2 * j] * kTsun;
-  const double q = params[2 * j + 1];
+  p.Mt = params[2 * pj] * kTsun;
+  const double q = params[2 * pj + 1];
   p.eta = q / ((1.0 + q) * (1.0 + q));
   dd acc = {0.0, 0.0};
   double2* o64 = reinterpret_cast<double2*>(out) + j * ld;
@@ -78,14 +81,14 @@ __global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restric
 
 }  // namespace
 
-hipError_t launch_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64_t N, int dtype,
-                             void* out, int64_t ld, hipStream_t s) {
+hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, double flo, double fhi, int64_t N,
+                             int dtype, void* out, int64_t ld, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   if (M > 0x7fffffffLL) return hipErrorInvalidValue;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_chirp<0>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, M, flo, fhi, N, out, ld);
+    hipLaunchKernelGGL(k_chirp<0>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, flo, fhi, N, out, ld);
   else
-    hipLaunchKernelGGL(k_chirp<1>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, M, flo, fhi, N, out, ld);
+    hipLaunchKernelGGL(k_chirp<1>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, flo, fhi, N, out, ld);
   return hipGetLastError();
 }
 

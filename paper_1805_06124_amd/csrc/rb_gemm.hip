@@ -2,10 +2,11 @@
 //   project : C = E^H S  (k x M), the coefficients of every snapshot on the
 //             basis (the projection E E^H s of Sec. 4), on FP64 matrix cores
 //             (v_mfma_f64_16x16x4f64);
-//   deflate : W = X - E C (N x M), an explicit re-anchoring of the working
-//             columns onto their residuals against a panel of m basis
-//             vectors, i.e. the stored-residual form of the greedy (the
-//             residual matrix V of Alg. 2; Remark 5.5).
+//   resid   : W = X - E C (N x M) with exact norms of the result, the
+//             explicit re-anchoring of the working columns onto their
+//             residuals against m basis vectors, i.e. the stored-residual
+//             form of the greedy (the residual matrix V of Alg. 2;
+//             Remark 5.5).
 #include "rb_internal.h"
 
 namespace rb {
@@ -97,41 +98,148 @@ __global__ __launch_bounds__(256) void k_project_z(const double2* __restrict__ E
       }
 }
 
-// ------------------------------------------------------------- deflate --
-// W[n, j] = X[n, j] - sum_{i<m} E[n, i] C(i, j), C(i, j) = C[i*cI + j*cJ].
-// One thread per row n, kDefCols columns per workgroup; the coefficients of
-// a column are uniform over the workgroup.
-constexpr int kDefCols = 16;
+// ------------------------------------------------------------- residual --
+// Explicit re-anchoring of a block of working columns:
+//   W[:, j] = X[:, j] - E[:, 0:m] C(0:m, j),  nrm[j] = ||W[:, j]||^2 (exact)
+// with C(i, j) = C[i*cI + j*cJ].  X and W may alias (in-place).  The norm is
+// that of the stored W values (after rounding to the output type),
+// accumulated as a double-double and rounded once.
+//
+// One workgroup owns a strip of 64 columns and walks down all rows in 64-row
+// tiles, so each column's norm is finished inside the workgroup (no partial
+// buffers, deterministic).  The product E C for a row tile runs on FP64
+// matrix cores: 4 waves as 2 x 2, each 32 x 32 = 2 x 2 MFMA 16x16 tiles,
+// the reduction over basis vectors in LDS-staged chunks of 16.
+//   E C, complex:  re = Er Cr - Ei Ci,  im = Er Ci + Ei Cr.
+constexpr int kRT = 64;   // rows per tile, columns per strip
+constexpr int kRK = 16;   // basis vectors per LDS chunk
 
-// X and W may alias (in-place re-anchoring): each element is read and then
-// written by the same thread.
-__global__ __launch_bounds__(256) void k_deflate_z(const double2* X, int64_t ldX,
-                                                   double2* W, int64_t ldW, int64_t N, int64_t M,
-                                                   const double2* __restrict__ E, int64_t ldE, int64_t m,
-                                                   const double2* __restrict__ Cc, int64_t cI, int64_t cJ) {
-  const int64_t n = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kDefCols;
-  if (n >= N) return;
-  double re[kDefCols], im[kDefCols];
+__device__ __forceinline__ double2 ld_x(const double2* p) { return ld_stream(p); }
+__device__ __forceinline__ double2 ld_x(const float2* p) {
+  float2 v = ld_stream(p);
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ double2 st_w(double2* p, double re, double im) {
+  *p = make_double2(re, im);
+  return make_double2(re, im);
+}
+__device__ __forceinline__ double2 st_w(float2* p, double re, double im) {
+  float2 v = make_float2((float)re, (float)im);
+  *p = v;
+  return make_double2((double)v.x, (double)v.y);
+}
+
+template <class XT, class WT>
+__global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, int64_t ldW, int64_t N, int64_t M,
+                                               const double2* __restrict__ E, int64_t ldE, int64_t m,
+                                               const double2* __restrict__ Cc, int64_t cI, int64_t cJ,
+                                               double* __restrict__ nrm, int* __restrict__ bad) {
+  // LDS: the staging chunks of E and C, reused as a half tile (32 columns x
+  // 64 rows) of the product for a coalesced epilogue.
+  constexpr int kStage = 2 * kRK * (kRT + 1);
+  constexpr int kHalf = (kRT / 2) * (kRT + 1);
+  __shared__ double2 smem[kStage > kHalf ? kStage : kHalf];
+  double2 (*sE)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem);
+  double2 (*sC)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem + kRK * (kRT + 1));
+  double2 (*sD)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int64_t j0 = (int64_t)blockIdx.x * kRT;
+
+  // wave w finishes columns j0 + 32 h + 8 w + c (h = 0, 1; c < 8), lane =
+  // row; each row tile's column sums are folded into snorm (one slot per
+  // column, owned by one wave)
+  __shared__ dd snorm[kRT];
+  if (tid < kRT) snorm[tid] = {0.0, 0.0};
+
+  for (int64_t n0 = 0; n0 < N; n0 += kRT) {
+    d4v accr[2][2], acci[2][2];
 #pragma unroll
-  for (int c = 0; c < kDefCols; ++c) re[c] = im[c] = 0.0;
-  int64_t jc[kDefCols];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-  for (int c = 0; c < kDefCols; ++c) jc[c] = (j0 + c < M) ? j0 + c : M - 1;
-  for (int64_t i = 0; i < m; ++i) {
-    const double2 a = E[n + i * ldE];
+      for (int b = 0; b < 2; ++b) {
+        accr[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+        acci[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+      }
+    for (int64_t i0 = 0; i0 < m; i0 += kRK) {
+      // stage E[n0:n0+64, i0:i0+16] and C(i0:i0+16, j0:j0+64)
 #pragma unroll
-    for (int c = 0; c < kDefCols; ++c) {
-      const double2 g = Cc[i * cI + jc[c] * cJ];
-      re[c] += a.x * g.x - a.y * g.y;
-      im[c] += a.x * g.y + a.y * g.x;
+      for (int q = 0; q < (kRT * kRK) / 256; ++q) {
+        const int idx = tid + 256 * q;
+        const int r = idx % kRT, kk = idx / kRT;
+        const int64_t n = n0 + r, i = i0 + kk, j = j0 + r;
+        double2 ev = make_double2(0.0, 0.0), cv = make_double2(0.0, 0.0);
+        if (i < m) {
+          if (n < N) ev = E[n + i * ldE];
+          if (j < M) cv = Cc[i * cI + j * cJ];
+        }
+        sE[kk][r] = ev;
+        sC[kk][r] = cv;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kRK; kk += 4) {
+        const int r = kk + (lane >> 4);
+        double2 a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = sE[r][wr * 32 + 16 * t + (lane & 15)];
+          b[t] = sC[r][wc * 32 + 16 * t + (lane & 15)];
+        }
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb) {
+            accr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].x, accr[ta][tb], 0, 0, 0);
+            accr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ta].y, b[tb].y, accr[ta][tb], 0, 0, 0);
+            acci[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].y, acci[ta][tb], 0, 0, 0);
+            acci[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].y, b[tb].x, acci[ta][tb], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+    // epilogue in two column halves through LDS: W = X - E C, column-wise
+    // (lane = row) so every load/store of a wave is one contiguous run
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (wc == h) {
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              sD[16 * tb + (lane & 15)][wr * 32 + 16 * ta + (lane >> 4) + 4 * r] =
+                  make_double2(accr[ta][tb][r], acci[ta][tb][r]);
+      }
+      __syncthreads();
+      const int64_t n = n0 + lane;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int cl = 8 * wave + c;
+        const int64_t j = j0 + 32 * h + cl;
+        dd part = {0.0, 0.0};
+        if (j < M && n < N) {
+          const double2 d = sD[cl][lane];
+          const double2 x = ld_x(X + n + j * ldX);
+          const double2 w = st_w(W + n + j * ldW, x.x - d.x, x.y - d.y);
+          dd_add_sq(part, w.x);
+          dd_add_sq(part, w.y);
+        }
+        part = wave_dd_sum(part);
+        if (lane == 0) snorm[32 * h + cl] = dd_add(snorm[32 * h + cl], part);
+      }
+      __syncthreads();
     }
   }
-#pragma unroll
-  for (int c = 0; c < kDefCols; ++c) {
-    if (j0 + c < M) {
-      const double2 x = X[n + (j0 + c) * ldX];
-      W[n + (j0 + c) * ldW] = make_double2(x.x - re[c], x.y - im[c]);
+  if (tid < kRT) {
+    const int64_t j = j0 + tid;
+    if (j < M) {
+      const dd t = snorm[tid];
+      const double r = t.hi + t.lo;
+      nrm[j] = r;
+      if (!__builtin_isfinite(r)) *bad = 1;  // same value from every writer
     }
   }
 }
@@ -147,13 +255,30 @@ hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE,
   return hipGetLastError();
 }
 
-hipError_t launch_deflate_z(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
-                            const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
-                            hipStream_t s) {
-  dim3 grid((unsigned)((M + kDefCols - 1) / kDefCols), (unsigned)((N + 255) / 256));
-  if (grid.y > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_deflate_z, grid, dim3(256), 0, s, X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ);
+template <class XT, class WT>
+hipError_t launch_resid_t(const XT* X, int64_t ldX, WT* W, int64_t ldW, int64_t N, int64_t M, const double2* E,
+                          int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ, double* nrm, int* bad,
+                          hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  dim3 grid((unsigned)((M + kRT - 1) / kRT));
+  hipLaunchKernelGGL((k_resid<XT, WT>), grid, dim3(256), 0, s, X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ, nrm, bad);
   return hipGetLastError();
+}
+
+hipError_t launch_resid(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s) {
+  return launch_resid_t(X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ, nrm, bad, s);
+}
+hipError_t launch_resid(const double2* X, int64_t ldX, float2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s) {
+  return launch_resid_t(X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ, nrm, bad, s);
+}
+hipError_t launch_resid(const float2* X, int64_t ldX, float2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s) {
+  return launch_resid_t(X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ, nrm, bad, s);
 }
 
 }  // namespace rb

@@ -1,0 +1,93 @@
+// Host-side helpers shared by the C-ABI translation units (error state,
+// RAII device/pinned buffers, event timers).
+#pragma once
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "rb_internal.h"
+
+namespace rb {
+
+// per-thread message of the last failing call
+std::string& last_error();
+int set_error(int code, const char* fmt, ...);
+
+#define RB_HIP(expr)                                                                                \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return ::rb::set_error(RB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Device buffer owned by one call.
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+// Pinned host buffer owned by one call.
+struct HostBuf {
+  void* p = nullptr;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipHostMalloc(&p, bytes, hipHostMallocDefault); }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+#define RB_ALLOC(buf, bytes)                                                                         \
+  do {                                                                                               \
+    if ((buf).alloc(bytes) != hipSuccess) {                                                          \
+      (void)hipGetLastError();                                                                       \
+      return ::rb::set_error(RB_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes));   \
+    }                                                                                                \
+  } while (0)
+
+// Accumulates device time between start() and stop() with HIP events on one
+// stream (stop() synchronises on its event); inactive unless enabled.
+struct EventTimer {
+  bool on = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s = nullptr;
+  EventTimer(bool enable, hipStream_t st) : on(enable), s(st) {
+    if (on) {
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) on = false;
+    }
+  }
+  ~EventTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  void start() {
+    if (on) (void)hipEventRecord(a, s);
+  }
+  void stop(double* acc) {
+    if (!on) return;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    *acc += ms;
+  }
+};
+
+inline bool valid_ld(int64_t N, int64_t ld) { return ld >= N && ld > 0; }
+
+}  // namespace rb

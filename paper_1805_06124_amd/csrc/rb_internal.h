@@ -108,8 +108,13 @@ struct ArgMax {
   int64_t i;
 };
 
+// Candidates kept by the mixed-precision sweep for FP64 confirmation.
+constexpr int kTop = 8;
+
 // launchers (each defined in the translation unit that holds the kernel)
 hipError_t launch_colnorms_z(const double2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
+                             hipStream_t s);
+hipError_t launch_colnorms_c(const float2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
                              hipStream_t s);
 hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* e,
                           const double* nrm, double* acc, const uint8_t* mask, double2* c_out, int64_t ldc,
@@ -117,6 +122,17 @@ hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, c
 hipError_t launch_est_argmax(const double* nrm, const double* acc, const uint8_t* mask, int64_t M,
                              ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
 int64_t sweep_partials_needed(int64_t M);
+
+// mixed precision: complex64 sweep with FP32 basis copy -> kTop best
+// (est, index) in top[0..kTop) (descending, ties to the lower index)
+hipError_t launch_sweep_c(const float2* S, int64_t N, int64_t M, int64_t ldS, const float2* e, const double* nrm,
+                          double* acc, const uint8_t* mask, double2* c_out, int64_t ldc, ArgMax* partial,
+                          int64_t cap, ArgMax* top, hipStream_t s);
+hipError_t launch_est_topk(const double* nrm, const double* acc, const uint8_t* mask, int64_t M, ArgMax* partial,
+                           int64_t cap, ArgMax* top, hipStream_t s);
+int64_t sweep32_partials_needed(int64_t M);
+hipError_t launch_round32(const double2* x, int64_t N, float2* y, hipStream_t s);
+hipError_t launch_iota(int64_t* cols, int64_t start, int64_t n, hipStream_t s);
 
 // Gram-Schmidt building blocks over the basis E (N x k, ldE) and nv vectors
 // V (N x nv, ldV):  G = E^H V ;  V -= E G ;  norms.
@@ -129,15 +145,23 @@ hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64
 hipError_t launch_scale_into(const double2* v, int64_t N, const double* sq, double2* out, hipStream_t s);
 
 // Re-anchoring: W[:, j] = X[:, j] - sum_{i<m} E[:, i] C(i, j) with
-// C(i, j) = C[i*cI + j*cJ]  (X may equal W)
-hipError_t launch_deflate_z(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
-                            const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
-                            hipStream_t s);
+// C(i, j) = C[i*cI + j*cJ] (X may equal W), nrm[j] = exact ||W[:, j]||^2;
+// *bad set to 1 if a norm is not finite.
+hipError_t launch_resid(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s);
+hipError_t launch_resid(const double2* X, int64_t ldX, float2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s);
+hipError_t launch_resid(const float2* X, int64_t ldX, float2* W, int64_t ldW, int64_t N, int64_t M,
+                        const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
+                        double* nrm, int* bad, hipStream_t s);
 // C = E^H S on FP64 matrix cores
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s);
 
-hipError_t launch_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64_t N, int dtype,
-                             void* out, int64_t ld, hipStream_t s);
+// cols (device, may be NULL): output column j uses parameter set cols[j]
+hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, double flo, double fhi, int64_t N,
+                             int dtype, void* out, int64_t ld, hipStream_t s);
 
 }  // namespace rb

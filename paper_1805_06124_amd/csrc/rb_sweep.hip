@@ -28,15 +28,22 @@ __device__ __forceinline__ void cmac_conj(const double2 e, const double2 s, doub
 // --------------------------------------------------------------------------
 // Exact squared column norms.  One wave per column; every lane accumulates a
 // double-double sum of its rows, then the wave combines the 64 partial sums.
-__global__ __launch_bounds__(256) void k_colnorms_z(const double2* __restrict__ S, int64_t N, int64_t M,
-                                                     int64_t ldS, double* __restrict__ nrm, int* __restrict__ bad) {
+__device__ __forceinline__ double2 ld_c(const double2* p) { return ld_stream(p); }
+__device__ __forceinline__ double2 ld_c(const float2* p) {
+  const float2 v = ld_stream(p);
+  return make_double2((double)v.x, (double)v.y);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_colnorms(const T* __restrict__ S, int64_t N, int64_t M, int64_t ldS,
+                                                  double* __restrict__ nrm, int* __restrict__ bad) {
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (j >= M) return;
-  const double2* col = S + j * ldS;
+  const T* col = S + j * ldS;
   dd acc = {0.0, 0.0};
   for (int64_t n = lane; n < N; n += 64) {
-    double2 v = ld_stream(col + n);
+    const double2 v = ld_c(col + n);
     dd_add_sq(acc, v.x);
     dd_add_sq(acc, v.y);
   }
@@ -181,12 +188,20 @@ int64_t sweep_partials_needed(int64_t M) {
   return a > b ? a : b;
 }
 
-hipError_t launch_colnorms_z(const double2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
-                             hipStream_t s) {
+template <class T>
+hipError_t launch_colnorms_t(const T* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad, hipStream_t s) {
   const int waves = 4;
   int64_t grid = (M + waves - 1) / waves;
-  hipLaunchKernelGGL(k_colnorms_z, dim3((unsigned)grid), dim3(64 * waves), 0, s, S, N, M, ldS, nrm, bad);
+  hipLaunchKernelGGL(k_colnorms<T>, dim3((unsigned)grid), dim3(64 * waves), 0, s, S, N, M, ldS, nrm, bad);
   return hipGetLastError();
+}
+hipError_t launch_colnorms_z(const double2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
+                             hipStream_t s) {
+  return launch_colnorms_t(S, N, M, ldS, nrm, bad, s);
+}
+hipError_t launch_colnorms_c(const float2* S, int64_t N, int64_t M, int64_t ldS, double* nrm, int* bad,
+                             hipStream_t s) {
+  return launch_colnorms_t(S, N, M, ldS, nrm, bad, s);
 }
 
 hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* e,

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(L):
 def test_default_opts_and_strerror(L):
     o = rbm.Opts()
     L.rb_default_opts(ctypes.byref(o))
-    assert o.kappa == 2.0 and o.nu_max == 4 and o.nu_min == 1 and o.anchor_max == 64
+    assert o.kappa == 2.0 and o.nu_max == 4 and o.nu_min == 1 and o.anchor_max == 128
     assert 0 < o.theta < 1
     assert b"invalid" in L.rb_strerror(-1)
     assert b"kmax" in L.rb_strerror(1)

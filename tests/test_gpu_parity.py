@@ -35,7 +35,7 @@ def _gpu_greedy_and_replay(rb, S_host, tol, kmax, **opts):
     return g, ref
 
 
-def _check_replay(g, ref, S_host, theta=1e-3, am=64):
+def _check_replay(g, ref, S_host, theta=1e-3, am=128):
     k = g["k"]
     A = float(oracle.sqnorms(S_host).max())
     res = 16 * (am + 1) * U / theta
