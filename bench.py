@@ -56,13 +56,45 @@ def cpu_baseline(w, m_slice, steps, log):
                       % (k, m_slice, w.name, w.N, dt, w.M / m_slice, w.M)}
 
 
+def sweep32_bytes(N, M):
+    # S32 once (8 N M), e32 (8 N), nrm read, acc read+write, mask, coefficient
+    # write (FP64)
+    return 8 * N * M + 8 * N + (8 + 16 + 1 + 16) * M
+
+
+def timed_runs(fn, steps, warmup, log, tag):
+    import torch
+    runs = []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log("%s %s run %d: k=%d status=%s err_k=%.3e anchors=%d (exact %d) misses=%d %.3f s" % (
+            tag, "warmup" if i < warmup else "timed", i, g["k"], g["status"], g["err"][-1],
+            g["stats"]["anchors"], g["stats"].get("regen_anchors", 0), g["stats"].get("misses", 0), dt))
+        if i >= warmup:
+            runs.append((dt, g))
+    return runs
+
+
+def orthogonality(E):
+    import torch
+    k = E.shape[0]
+    G = E.conj() @ E.T
+    return float(torch.linalg.matrix_norm(G - torch.eye(k, dtype=G.dtype, device=G.device), ord=2))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chirp_10k_409600_c128")
+    ap.add_argument("--tol", type=float, default=None, help="override the workload's tol")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-slice", type=int, default=51200)
     ap.add_argument("--cpu-steps", type=int, default=80)
     args = ap.parse_args()
@@ -82,70 +114,91 @@ def main():
 
     rb.load()
     w = ri.WORKLOADS[args.workload]
-    if w.dtype != "c128":
-        raise SystemExit("only complex128 workloads are wired into this benchmark")
+    tol = w.tol if args.tol is None else args.tol
     dev = torch.device("cuda:0")
-    log("generating %s: N=%d M=%d (%.1f GB)" % (w.name, w.N, w.M, 16 * w.N * w.M / 1e9))
     params = torch.from_numpy(w.params()).to(dev)
-    S = rb.chirp_fill(params, w.N, w.flo, w.fhi)
-    Wk = torch.empty_like(S)
-    torch.cuda.synchronize()
+    out = {
+        "metric": "RB greedy steps/s + sweep HBM GB/s, FP64 vs mixed at equal 1e-10 error",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "data": "synthetic",
+    }
+    fp64 = None
+    if w.dtype == "c128":
+        log("generating %s: N=%d M=%d (%.1f GB complex128)" % (w.name, w.N, w.M, 16 * w.N * w.M / 1e9))
+        S = rb.chirp_fill(params, w.N, w.flo, w.fhi)
+        Wk = torch.empty_like(S)
+        runs = timed_runs(lambda: rb.greedy(S, tol, w.kmax, W=Wk), args.steps, args.warmup, log, "fp64")
+        t_run = sum(dt for dt, _ in runs) / len(runs)
+        g = runs[-1][1]
+        gs = rb.greedy(S, tol, w.kmax, W=Wk, collect_stats=1)
+        st = gs["stats"]
+        ms = st["ms_sweep"] / max(st["sweeps"], 1)
+        by = sweep_bytes(w.N, w.M)
+        fp64 = dict(value=sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), time_to_tol_s=t_run,
+                    k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
+                    anchors=int(g["stats"]["anchors"]), orthogonality=orthogonality(g["E"]),
+                    roofline={"kernel": "k_sweep_z", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                              "ms_per_launch": ms, "bytes_per_launch": by},
+                    breakdown_ms={"sweep": st["ms_sweep"], "gs": st["ms_gs"], "anchor": st["ms_anchor"],
+                                  "total": st["ms_total"]})
+        log("fp64 sweep: %.3f ms/launch, %.1f GB/s; gs %.1f ms, anchors %.1f ms (%d)" % (
+            ms, fp64["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"]))
+        del S, Wk, g, gs, runs
+        torch.cuda.empty_cache()
 
-    runs = []
-    for i in range(args.warmup + args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = rb.greedy(S, w.tol, w.kmax, W=Wk)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        log("%s run %d: k=%d status=%s err_k=%.3e anchors=%d %.3f s" % (
-            "warmup" if i < args.warmup else "timed", i, g["k"], g["status"], g["err"][-1],
-            g["stats"]["anchors"], dt))
-        if i >= args.warmup:
-            runs.append((dt, g))
-    total_t = sum(dt for dt, _ in runs)
-    total_iters = sum(g["k"] for _, g in runs)
-    value = total_iters / total_t
-    g_last = runs[-1][1]
-
-    # per-launch sweep timing: HIP events inside the library, on its stream
-    gs = rb.greedy(S, w.tol, w.kmax, W=Wk, collect_stats=1)
-    st = gs["stats"]
-    ms_sweep = st["ms_sweep"] / max(st["sweeps"], 1)
-    bytes_sweep = sweep_bytes(w.N, w.M)
-    achieved = bytes_sweep / (ms_sweep * 1e-3) / 1e9
-    log("sweep: %.3f ms/launch, %.1f GB/s; gs %.2f ms total, anchors %.2f ms total (%d)" % (
-        ms_sweep, achieved, st["ms_gs"], st["ms_anchor"], st["anchors"]))
+    mixed = None
+    if w.dtype == "c64" or not args.no_mixed:
+        log("generating complex64 storage: N=%d M=%d (%.1f GB)" % (w.N, w.M, 8 * w.N * w.M / 1e9))
+        S32 = rb.chirp_fill(params, w.N, w.flo, w.fhi, dtype=torch.complex64)
+        W32 = torch.empty_like(S32)
+        runs = timed_runs(lambda: rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32), args.steps,
+                          args.warmup, log, "mixed")
+        t_run = sum(dt for dt, _ in runs) / len(runs)
+        g = runs[-1][1]
+        gs = rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32, collect_stats=1)
+        st = gs["stats"]
+        ms = st["ms_sweep"] / max(st["sweeps"], 1)
+        by = sweep32_bytes(w.N, w.M)
+        mixed = dict(value=sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), time_to_tol_s=t_run,
+                     k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
+                     anchors=int(g["stats"]["anchors"]), exact_anchors=int(g["stats"]["regen_anchors"]),
+                     misses=int(g["stats"]["misses"]), orthogonality=orthogonality(g["E"]),
+                     roofline={"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "ms_per_launch": ms, "bytes_per_launch": by},
+                     breakdown_ms={"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
+                                   "total": st["ms_total"]})
+        log("mixed sweep: %.3f ms/launch, %.1f GB/s; confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (
+            ms, mixed["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
+        del S32, W32, g, gs, runs
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        del Wk
         cpu = cpu_baseline(w, args.cpu_slice, args.cpu_steps, log)
 
-    out = {
-        "metric": "RB greedy steps/s + sweep HBM GB/s, FP64 vs mixed at equal 1e-10 error",
-        "value": value,
-        "unit": "steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total_t / len(runs),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "M": w.M, "storage": "complex128", "tol": w.tol,
-                   "kmax": w.kmax, "k": int(g_last["k"]), "status": g_last["status"],
-                   "err_final": float(g_last["err"][-1]), "anchors": int(g_last["stats"]["anchors"]),
+    main_leg = fp64 if fp64 is not None else mixed
+    out.update({
+        "value": main_leg["value"], "unit": "steps/s",
+        "ms_per_step": 1e3 * main_leg["time_to_tol_s"],
+        "dtype": "f64" if fp64 is not None else "f32+f64",
+        "config": {"workload": w.name, "N": w.N, "M": w.M,
+                   "storage": "complex128" if fp64 is not None else "complex64", "tol": tol, "kmax": w.kmax,
+                   "k": main_leg["k"], "status": main_leg["status"], "err_final": main_leg["err_final"],
+                   "anchors": main_leg["anchors"],
                    "step": "one full greedy run to tol (S resident in HBM)"},
-        "roofline": {"kernel": "k_sweep_z", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "ms_per_launch": ms_sweep, "bytes_per_launch": bytes_sweep},
-        "breakdown_ms": {"sweep": st["ms_sweep"], "gs": st["ms_gs"], "anchor": st["ms_anchor"],
-                         "total": st["ms_total"]},
+        "roofline": main_leg["roofline"],
+        "breakdown_ms": main_leg["breakdown_ms"],
         "cpu_baseline": cpu,
-    }
+    })
+    if fp64 is not None and mixed is not None:
+        out["mixed"] = {"workload": w.name.replace("c128", "c64"), "storage": "complex64", **mixed,
+                        "speedup_time_to_tol_vs_fp64": fp64["time_to_tol_s"] / mixed["time_to_tol_s"],
+                        "equal_error": bool(fp64["err_final"] < tol and mixed["err_final"] < tol)}
+        out["fp64_orthogonality"] = fp64["orthogonality"]
     print(json.dumps(out), flush=True)
 
 

@@ -75,10 +75,12 @@ typedef struct rb_opts {
                           exact re-anchoring (scratch: regen_chunk x N
                           complex128 plus kmax x regen_chunk complex128).
                           Default 32768. */
-  int32_t certify;    /* 1: before returning converged, recompute every
+  int32_t certify;    /* before returning converged: 1 = recompute every
                          column's residual exactly in FP64 from regenerated
-                         columns and continue if it is still >= tol.
-                         Default 1. */
+                         columns and continue if one is still >= tol; 2 =
+                         the same, unless the sweep's largest estimate plus
+                         its rounding and perturbation bound is already
+                         below tol^2; 0 = no check.  Default 2. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */

@@ -58,7 +58,7 @@ void rb_default_opts(rb_opts* o) {
   o->collect_stats = 0;
   o->theta32 = 1e-4;
   o->regen_chunk = 32768;
-  o->certify = 1;
+  o->certify = 2;
 }
 
 const char* rb_strerror(int status) {

@@ -281,9 +281,23 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
   err[0] = (Jbest >= 0) ? rbest : 0.0;
   bool certified = false;
 
+  // Bound on |est_j - true residual_j^2| for the stored columns since the
+  // last anchoring: FP32 coefficients (|dc| <= 9 u32 ||x_j||, so the m
+  // accumulated |c|^2 terms are off by <= 18 sqrt(m) u32 nrm_j) plus the
+  // stored-column perturbation P (|d ||r||^2| <= 2 ||r|| P + P^2).
+  auto est_bound = [&](double est) -> double {
+    const double u32 = 0x1p-24;
+    const double r = std::sqrt(est > 0.0 ? est : 0.0);
+    return 18.0 * std::sqrt((double)(m > 0 ? m : 1)) * u32 * A_w + 2.0 * r * P + P * P;
+  };
+
   while (true) {
     if (err[k] < tol) {
-      if (o.certify && !certified && k < kcap && Jbest >= 0) {
+      // certify == 2: the sweep's largest estimate already bounds every
+      // column's true residual below tol
+      const bool bounded_ok = o.certify == 2 && h_top[0].i >= 0 &&
+                              h_top[0].v + est_bound(h_top[0].v) < tol * tol;
+      if (o.certify && !certified && !bounded_ok && k < kcap && Jbest >= 0) {
         rc = anchor(true);
         if (rc != RB_OK) return rc;
         certified = true;

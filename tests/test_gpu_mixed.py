@@ -107,7 +107,7 @@ def test_greedy_c_small_chirp(rb, tol):
     assert abs(g["k"] - free["k"]) <= 2, (g["k"], free["k"])
 
 
-@pytest.mark.parametrize("opts", [dict(certify=0), dict(anchor_max=4), dict(theta32=1e-2), dict(regen_chunk=77)])
+@pytest.mark.parametrize("opts", [dict(certify=0), dict(certify=1), dict(anchor_max=4), dict(theta32=1e-2), dict(regen_chunk=77)])
 def test_greedy_c_options(rb, opts):
     w, P, S64 = _small(M=900, N=700)
     g, _ = _mixed_vs_oracle(rb, w, P, S64, 1e-10, **opts)
