@@ -257,6 +257,61 @@ int rb_project_z(const void *E, int64_t N, int64_t k, int64_t ldE, const void *S
 int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64_t N, int dtype, void *out,
                   int64_t ld, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned coefficient surrogate (not part of the paper's method: an MLP that
+ * predicts the projection coefficients c = E^H s of a snapshot from its
+ * parameters, with the plain projection of the regenerated snapshot as the
+ * judge and fallback).  Network din -> hidden -> hidden -> hidden -> dout,
+ * tanh hidden layers, linear output; BF16 weights and activations, FP32
+ * accumulation on BF16 matrix cores, FP32 master weights for Adam.
+ *
+ * Parameters: one FP32 buffer p32 and one BF16 buffer p16 (uint16 bit
+ * patterns) of rb_mlp_param_count() entries, laid out row-major [in][out]:
+ * W1 (din x hidden), b1, W2 (hidden x hidden), b2, W3, b3,
+ * W4 (hidden x dout), b4.  Inputs X: FP32 [batch][din]; outputs Y: FP32
+ * [batch][dout].  The workspace ws (device, rb_mlp_workspace_bytes())
+ * keeps the activations of the last forward for the backward pass and for
+ * rb_mlp_loss.  1 <= din <= 4.
+ * ---------------------------------------------------------------------- */
+int64_t rb_mlp_param_count(int din, int hidden, int dout);
+size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout);
+
+/* Y = MLP(X) (Y may be NULL: kept in the workspace). */
+int rb_mlp_forward(const float *p32, const uint16_t *p16, int din, int hidden, int dout, const float *X,
+                   int64_t batch, float *Y, void *ws, hipStream_t stream);
+
+/* Mean squared error over batch x dout of Y - T into *loss (device float)
+ * and its gradient dY = 2 (Y - T) / (batch dout) as BF16 (dY NULL: kept in
+ * the workspace).  Y NULL: the workspace output of the last forward. */
+int rb_mlp_loss(const float *Y, const float *T, int64_t batch, int dout, uint16_t *dY, float *loss, void *ws,
+                int din, int hidden, hipStream_t stream);
+
+/* Gradients of the loss w.r.t. all parameters into grad (FP32, p32 layout),
+ * given dY (BF16; NULL = the workspace's) and the activations of the last
+ * forward on the same X. */
+int rb_mlp_backward(const float *p32, const uint16_t *p16, int din, int hidden, int dout, const float *X,
+                    int64_t batch, const uint16_t *dY, float *grad, void *ws, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected) on the FP32 master p32 with
+ * moments m, v; refreshes the BF16 copy p16.  step >= 1. */
+int rb_mlp_adam(float *p32, uint16_t *p16, const float *grad, float *m, float *v, int64_t n, float lr, float beta1,
+                float beta2, float eps, int64_t step, hipStream_t stream);
+
+/* Batch gather: X[b] = params[idx[b]] (2 doubles) mapped affinely from
+ * [ranges[0], ranges[1]] x [ranges[2], ranges[3]] (host array) onto
+ * [-1, 1]^2; T[b] = targets[idx[b]] (dout floats) if targets != NULL. */
+int rb_mlp_gather(const double *params, const float *targets, const int64_t *idx, int64_t batch, int dout,
+                  const double *ranges, float *X, float *T, hipStream_t stream);
+
+/* Coefficients C (complex128, sample j at C[j*ldc .. j*ldc+k)) -> FP32
+ * targets T[j] = [Re c_j; Im c_j] (2k floats per sample). */
+int rb_coef_targets(const void *C, int64_t ldc, int64_t Mn, int k, float *T, hipStream_t stream);
+
+/* Per-sample relative coefficient error ||c_hat_j - c_j|| / ||c_j|| in
+ * FP64 (= the relative L2 waveform error of E c_hat_j for orthonormal E);
+ * Yh FP32 [Re; Im] per sample. */
+int rb_coef_relerr(const float *Yh, const void *C, int64_t ldc, int64_t Mn, int k, double *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,7 +50,9 @@ class ChirpCtx(ctypes.Structure):
 
 
 EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "rb_sweep_z", "rb_greedy_z",
-           "rb_sweep_c", "rb_greedy_c", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill"]
+           "rb_sweep_c", "rb_greedy_c", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
+           "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
+           "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr"]
 
 _lib = None
 
@@ -89,6 +91,25 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_project_z.argtypes = [P, I64, I64, I64, P, I64, I64, P, I64, P]
     L.rb_chirp_fill.restype = ctypes.c_int
     L.rb_chirp_fill.argtypes = [P, I64, D, D, I64, ctypes.c_int, P, I64, P]
+    C_INT, F = ctypes.c_int, ctypes.c_float
+    L.rb_mlp_param_count.restype = I64
+    L.rb_mlp_param_count.argtypes = [C_INT, C_INT, C_INT]
+    L.rb_mlp_workspace_bytes.restype = ctypes.c_size_t
+    L.rb_mlp_workspace_bytes.argtypes = [I64, C_INT, C_INT, C_INT]
+    L.rb_mlp_forward.restype = C_INT
+    L.rb_mlp_forward.argtypes = [P, P, C_INT, C_INT, C_INT, P, I64, P, P, P]
+    L.rb_mlp_loss.restype = C_INT
+    L.rb_mlp_loss.argtypes = [P, P, I64, C_INT, P, P, P, C_INT, C_INT, P]
+    L.rb_mlp_backward.restype = C_INT
+    L.rb_mlp_backward.argtypes = [P, P, C_INT, C_INT, C_INT, P, I64, P, P, P, P]
+    L.rb_mlp_adam.restype = C_INT
+    L.rb_mlp_adam.argtypes = [P, P, P, P, P, I64, F, F, F, F, I64, P]
+    L.rb_mlp_gather.restype = C_INT
+    L.rb_mlp_gather.argtypes = [P, P, P, I64, C_INT, P, P, P, P]
+    L.rb_coef_targets.restype = C_INT
+    L.rb_coef_targets.argtypes = [P, I64, I64, C_INT, P, P]
+    L.rb_coef_relerr.restype = C_INT
+    L.rb_coef_relerr.argtypes = [P, P, I64, I64, C_INT, P, P]
     return L
 
 

@@ -1,0 +1,494 @@
+// Learned coefficient surrogate: an MLP (Mtot, q) -> [Re c; Im c] with
+// layers din -> hidden -> hidden -> hidden -> dout, tanh hidden activations,
+// BF16 weights and activations, FP32 accumulation and FP32 master weights.
+// The hidden and output layers run on BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16); the first layer (din = 2) and the column sums
+// are vector kernels.
+//
+// Parameter layout (FP32 master and BF16 copy share offsets), row-major
+// [in][out]:  W1 (din x h), b1 (h), W2 (h x h), b2, W3 (h x h), b3,
+// W4 (h x dout), b4 (dout).  Activations are row-major [batch][feature].
+#include <cmath>
+
+#include "rb_host.h"
+
+namespace rb {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- GEMM --
+// C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak],
+// B(k, n) = B[k*sbk + n*sbn], BF16 operands, FP32 accumulation.
+// Block tile 64 x 64, 4 waves as 2 x 2 (32 x 32 each = 2 x 2 MFMA tiles),
+// K chunks of 32 staged in LDS as [row][k] so that each lane's 8 operand
+// values are one 16-byte read.
+// v_mfma_f32_16x16x32_bf16: A lane l holds A[l%16][8(l/16) .. +7],
+// B lane l holds B[8(l/16) .. +7][l%16], result lane l register r holds
+// D[4(l/16) + r][l%16].
+enum Epi { kEpiStore = 0, kEpiBiasTanh = 1, kEpiBias = 2, kEpiDTanh = 3 };
+
+constexpr int kGT = 64, kGK = 32, kGKP = kGK + 8;
+
+// Stage the 64 x 32 tile X(r0 + r, k0 + kk) = X[r*sr + k*sk] (r < 64,
+// kk < 32) into LDS as dst[r][kk].  vec: 1 = K contiguous (sk == 1), 2 = R
+// contiguous (sr == 1), with 16-byte aligned rows, else 0 (scalar loads).
+// Each thread moves 8 values.
+__device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64_t sr, int64_t sk, int64_t R,
+                                           int64_t K, int64_t r0, int64_t k0, int vec, uint16_t (*dst)[kGKP],
+                                           int tid) {
+  if (vec == 1) {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    const int64_t gr = r0 + r, gk = k0 + kk;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gr < R && gk + 7 < K) {
+      v = *reinterpret_cast<const uint4*>(X + gr * sr + gk);
+    } else if (gr < R) {
+      uint16_t t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = (gk + i < K) ? X[gr * sr + gk + i] : (uint16_t)0;
+      v = *reinterpret_cast<const uint4*>(t);
+    }
+    *reinterpret_cast<uint4*>(&dst[r][kk]) = v;
+  } else if (vec == 2) {
+    const int kk = tid >> 3, r = (tid & 7) * 8;
+    const int64_t gr = r0 + r, gk = k0 + kk;
+    uint16_t t[8];
+    if (gk < K && gr + 7 < R) {
+      *reinterpret_cast<uint4*>(t) = *reinterpret_cast<const uint4*>(X + gk * sk + gr);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = (gk < K && gr + i < R) ? X[gk * sk + gr + i] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[r + i][kk] = t[i];
+  } else {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    const int64_t gr = r0 + r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t gk = k0 + kk + i;
+      dst[r][kk + i] = (gr < R && gk < K) ? X[gr * sr + gk * sk] : (uint16_t)0;
+    }
+  }
+}
+
+template <int kEpi>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
+                                                   int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
+                                                   int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ Cb,
+                                                   int64_t ldcb, const uint16_t* __restrict__ H, int64_t ldh,
+                                                   int vecA, int vecB) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * kGT, n0 = (int64_t)blockIdx.x * kGT;
+  f4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t k0 = 0; k0 < K; k0 += kGK) {
+    stage_tile(A, sam, sak, M, K, m0, k0, vecA, sA, tid);
+    stage_tile(B, sbn, sbk, N, K, n0, k0, vecB, sB, tid);
+    __syncthreads();
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = *reinterpret_cast<const bf16x8*>(&sA[wm * 32 + 16 * t + (lane & 15)][8 * (lane >> 4)]);
+      b[t] = *reinterpret_cast<const bf16x8*>(&sB[wn * 32 + 16 * t + (lane & 15)][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 32 + 16 * ta + 4 * (lane >> 4) + r;
+        const int64_t n = n0 + wn * 32 + 16 * tb + (lane & 15);
+        if (m >= M || n >= N) continue;
+        float v = acc[ta][tb][r];
+        if (kEpi == kEpiStore) {
+          C[m * ldc + n] = v;
+        } else if (kEpi == kEpiBiasTanh) {
+          Cb[m * ldcb + n] = f2bf(tanhf(v + bias[n]));
+        } else if (kEpi == kEpiBias) {
+          C[m * ldc + n] = v + bias[n];
+        } else {
+          const float h = bf2f(H[m * ldh + n]);
+          Cb[m * ldcb + n] = f2bf(v * (1.f - h * h));
+        }
+      }
+}
+
+// first layer (din inputs, FP32 in): H1 = bf16(tanh(X W1 + b1))
+__global__ __launch_bounds__(256) void k_layer1_fwd(const float* __restrict__ X, int64_t B, int din,
+                                                    const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                    int h, uint16_t* __restrict__ H1) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= B * h) return;
+  const int64_t b = t / h;
+  const int o = (int)(t % h);
+  float z = b1[o];
+  for (int i = 0; i < din; ++i) z += X[b * din + i] * bf2f(W1[(int64_t)i * h + o]);
+  H1[t] = f2bf(tanhf(z));
+}
+
+// column sums over the batch of a BF16 matrix D (B x d): db[o] = sum_b D[b][o]
+// and, if X is given, dW[i][o] = sum_b X[b][i] D[b][o] (i < din).  Partial
+// sums per workgroup row chunk go to part[(chunk)(din+1) d], reduced by
+// k_colsum_final in a fixed order.
+constexpr int kColRows = 256;
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ D, int64_t B, int d,
+                                                const float* __restrict__ X, int din, float* __restrict__ part) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= d) return;
+  const int64_t b0 = (int64_t)blockIdx.y * kColRows;
+  const int64_t b1 = (b0 + kColRows < B) ? b0 + kColRows : B;
+  const int nx = X ? din : 0;
+  float s = 0.f, sx[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t b = b0; b < b1; ++b) {
+    const float v = bf2f(D[b * d + o]);
+    s += v;
+    for (int i = 0; i < nx; ++i) sx[i] += X[b * din + i] * v;
+  }
+  float* p = part + (int64_t)blockIdx.y * (nx + 1) * d;
+  p[o] = s;
+  for (int i = 0; i < nx; ++i) p[(int64_t)(i + 1) * d + o] = sx[i];
+}
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int64_t chunks, int64_t len,
+                                                      float* __restrict__ db, float* __restrict__ dW, int d) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= len) return;
+  float s = 0.f;
+  for (int64_t c = 0; c < chunks; ++c) s += part[c * len + t];
+  if (t < d)
+    db[t] = s;
+  else
+    dW[t - d] = s;
+}
+
+// MSE loss and its gradient: dY = bf16(2 (Y - T) / (B d)); per-block
+// partial sums of (Y - T)^2 into part[blockIdx.x]
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ T, int64_t n,
+                                             float scale, uint16_t* __restrict__ dY, float* __restrict__ part) {
+  float s = 0.f;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+    const float d = Y[t] - T[t];
+    s += d * d;
+    dY[t] = f2bf(2.f * d * scale);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ float sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+__global__ __launch_bounds__(256) void k_sum_final(const float* __restrict__ part, int64_t n, float scale,
+                                                   float* __restrict__ out) {
+  float s = 0.f;
+  for (int64_t t = threadIdx.x; t < n; t += 256) s += part[t];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ float sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (sh[0] + sh[1] + sh[2] + sh[3]) * scale;
+}
+
+// Adam with bias correction on the FP32 master copy; refreshes the BF16 copy
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, uint16_t* __restrict__ w16,
+                                              const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int64_t n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const float gt = g[t];
+  const float mt = b1 * m[t] + (1.f - b1) * gt;
+  const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+  m[t] = mt;
+  v[t] = vt;
+  const float wt = w[t] - lr * (mt / c1) / (sqrtf(vt / c2) + eps);
+  w[t] = wt;
+  w16[t] = f2bf(wt);
+}
+
+// batch gather: X[b] = affine map of params[idx[b]] onto [-1, 1]^2,
+// T[b] = targets[idx[b]] (dout floats)
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ params, const float* __restrict__ targets,
+                                                const int64_t* __restrict__ idx, int64_t B, int dout, double lo0,
+                                                double hi0, double lo1, double hi1, float* __restrict__ X,
+                                                float* __restrict__ T) {
+  const int64_t b = blockIdx.x;
+  const int64_t j = idx[b];
+  if (threadIdx.x == 0) {
+    X[2 * b] = (float)(2.0 * (params[2 * j] - lo0) / (hi0 - lo0) - 1.0);
+    X[2 * b + 1] = (float)(2.0 * (params[2 * j + 1] - lo1) / (hi1 - lo1) - 1.0);
+  }
+  if (targets)
+    for (int o = threadIdx.x; o < dout; o += 256) T[b * dout + o] = targets[j * dout + o];
+}
+
+// complex128 coefficients C (sample-major: C[j*ldc + i], i < k) -> FP32
+// targets T[j][i] = Re, T[j][k + i] = Im
+__global__ __launch_bounds__(256) void k_coef_targets(const double2* __restrict__ C, int64_t ldc, int64_t Mn, int k,
+                                                      float* __restrict__ T) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= Mn * k) return;
+  const int64_t j = t / k;
+  const int i = (int)(t % k);
+  const double2 c = C[j * ldc + i];
+  T[j * 2 * k + i] = (float)c.x;
+  T[j * 2 * k + k + i] = (float)c.y;
+}
+
+// per-sample relative error ||c_hat - c|| / ||c|| (FP64 sums), one wave per
+// sample; c complex128 (C[j*ldc + i]), c_hat FP32 [Re; Im]
+__global__ __launch_bounds__(256) void k_coef_relerr(const float* __restrict__ Yh, const double2* __restrict__ C,
+                                                     int64_t ldc, int64_t Mn, int k, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= Mn) return;
+  double num = 0.0, den = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    const double2 c = C[j * ldc + i];
+    const double dr = (double)Yh[j * 2 * k + i] - c.x;
+    const double di = (double)Yh[j * 2 * k + k + i] - c.y;
+    num += dr * dr + di * di;
+    den += c.x * c.x + c.y * c.y;
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane == 0) out[j] = den > 0.0 ? sqrt(num / den) : sqrt(num);
+}
+
+// vector-load mode of an operand X(r, k) = X[r*sr + k*sk] (see stage_tile)
+int vec_mode(const uint16_t* X, int64_t sr, int64_t sk) {
+  const bool al = (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  if (al && sk == 1 && (sr * 2) % 16 == 0) return 1;
+  if (al && sr == 1 && (sk * 2) % 16 == 0) return 2;
+  return 0;
+}
+
+template <int kEpi>
+hipError_t gemm(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                int64_t sbk, int64_t sbn, float* C, int64_t ldc, const float* bias, uint16_t* Cb, int64_t ldcb,
+                const uint16_t* H, int64_t ldh, hipStream_t s) {
+  dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT));
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
+  hipLaunchKernelGGL(k_gemm_bf16<kEpi>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Cb,
+                     ldcb, H, ldh, vecA, vecB);
+  return hipGetLastError();
+}
+
+struct Layout {
+  int64_t W1, b1, W2, b2, W3, b3, W4, b4, total;
+  Layout(int din, int h, int dout) {
+    W1 = 0;
+    b1 = W1 + (int64_t)din * h;
+    W2 = b1 + h;
+    b2 = W2 + (int64_t)h * h;
+    W3 = b2 + h;
+    b3 = W3 + (int64_t)h * h;
+    W4 = b3 + h;
+    b4 = W4 + (int64_t)h * dout;
+    total = b4 + dout;
+  }
+};
+
+hipError_t colsum(const uint16_t* D, int64_t B, int d, const float* X, int din, float* part, float* db, float* dW,
+                  hipStream_t s) {
+  const int64_t chunks = (B + kColRows - 1) / kColRows;
+  dim3 grid((unsigned)((d + 255) / 256), (unsigned)chunks);
+  hipLaunchKernelGGL(k_colsum, grid, dim3(256), 0, s, D, B, d, X, din, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t len = (int64_t)((X ? din : 0) + 1) * d;
+  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part, chunks, len, db, dW,
+                     d);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" {
+
+int64_t rb_mlp_param_count(int din, int hidden, int dout) {
+  if (din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return -1;
+  return Layout(din, hidden, dout).total;
+}
+
+size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
+  if (batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return 0;
+  const int64_t chunks = (batch + kColRows - 1) / kColRows;
+  const int64_t part = chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout);
+  // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums
+  return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout) * 2 + (size_t)batch * dout * 4 +
+         (size_t)(part + 4096) * 4 + 1024;
+}
+
+// Workspace carve-up (byte offsets) shared by forward and backward.
+static void carve(void* ws, int64_t batch, int din, int hidden, int dout, uint16_t** H, uint16_t** dz,
+                  uint16_t** dY, float** Y, float** part) {
+  (void)din;
+  char* p = static_cast<char*>(ws);
+  for (int l = 0; l < 3; ++l) {
+    H[l] = reinterpret_cast<uint16_t*>(p);
+    p += (size_t)batch * hidden * 2;
+  }
+  dz[0] = reinterpret_cast<uint16_t*>(p);
+  p += (size_t)batch * hidden * 2;
+  dz[1] = reinterpret_cast<uint16_t*>(p);
+  p += (size_t)batch * hidden * 2;
+  *dY = reinterpret_cast<uint16_t*>(p);
+  p += (size_t)batch * dout * 2;
+  p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~(uintptr_t)255);
+  *Y = reinterpret_cast<float*>(p);
+  p += (size_t)batch * dout * 4;
+  *part = reinterpret_cast<float*>(p);
+}
+
+int rb_mlp_forward(const float* p32, const uint16_t* p16, int din, int hidden, int dout, const float* X,
+                   int64_t batch, float* Y, void* ws, hipStream_t stream) {
+  last_error().clear();
+  if (!p32 || !p16 || !X || !ws || batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0)
+    return set_error(RB_EINVAL, "rb_mlp_forward: bad arguments");
+  const Layout L(din, hidden, dout);
+  uint16_t *H[3], *dz[2], *dY;
+  float *Yw, *part;
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part);
+  if (!Y) Y = Yw;
+  const int64_t n1 = batch * hidden;
+  hipLaunchKernelGGL(k_layer1_fwd, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, stream, X, batch, din,
+                     p16 + L.W1, p32 + L.b1, hidden, H[0]);
+  RB_HIP(hipGetLastError());
+  RB_HIP(gemm<kEpiBiasTanh>(batch, hidden, hidden, H[0], hidden, 1, p16 + L.W2, hidden, 1, nullptr, 0, p32 + L.b2,
+                            H[1], hidden, nullptr, 0, stream));
+  RB_HIP(gemm<kEpiBiasTanh>(batch, hidden, hidden, H[1], hidden, 1, p16 + L.W3, hidden, 1, nullptr, 0, p32 + L.b3,
+                            H[2], hidden, nullptr, 0, stream));
+  RB_HIP(gemm<kEpiBias>(batch, dout, hidden, H[2], hidden, 1, p16 + L.W4, dout, 1, Y, dout, p32 + L.b4, nullptr, 0,
+                        nullptr, 0, stream));
+  return RB_OK;
+}
+
+int rb_mlp_loss(const float* Y, const float* T, int64_t batch, int dout, uint16_t* dY_out, float* loss,
+                void* ws, int din, int hidden, hipStream_t stream) {
+  last_error().clear();
+  if (!T || !loss || !ws || batch <= 0 || dout <= 0 || din <= 0 || din > 4 || hidden <= 0)
+    return set_error(RB_EINVAL, "rb_mlp_loss: bad arguments");
+  uint16_t *H[3], *dz[2], *dY;
+  float *Yw, *part;
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part);
+  if (!Y) Y = Yw;
+  if (!dY_out) dY_out = dY;
+  const int64_t n = batch * (int64_t)dout;
+  int64_t grid = (n + 255) / 256;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)grid), dim3(256), 0, stream, Y, T, n, 1.f / (float)n, dY_out, part);
+  RB_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, stream, part, grid, 1.f / (float)n, loss);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, int dout, const float* X,
+                    int64_t batch, const uint16_t* dY_in, float* grad, void* ws, hipStream_t stream) {
+  last_error().clear();
+  if (!p32 || !p16 || !X || !grad || !ws || batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0)
+    return set_error(RB_EINVAL, "rb_mlp_backward: bad arguments");
+  const Layout L(din, hidden, dout);
+  uint16_t *H[3], *dz[2], *dY;
+  float *Yw, *part;
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part);
+  if (dY_in) dY = const_cast<uint16_t*>(dY_in);
+  // output layer: dW4 = H3^T dY, db4 = colsum(dY), dZ3 = (dY W4^T) * (1 - H3^2)
+  RB_HIP(gemm<kEpiStore>(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, grad + L.W4, dout, nullptr, nullptr, 0,
+                         nullptr, 0, stream));
+  RB_HIP(colsum(dY, batch, dout, nullptr, din, part, grad + L.b4, nullptr, stream));
+  RB_HIP(gemm<kEpiDTanh>(batch, hidden, dout, dY, dout, 1, p16 + L.W4, 1, dout, nullptr, 0, nullptr, dz[0], hidden,
+                         H[2], hidden, stream));
+  // hidden layer 3: dW3 = H2^T dZ3, db3, dZ2 = (dZ3 W3^T) * (1 - H2^2)
+  RB_HIP(gemm<kEpiStore>(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, grad + L.W3, hidden, nullptr,
+                         nullptr, 0, nullptr, 0, stream));
+  RB_HIP(colsum(dz[0], batch, hidden, nullptr, din, part, grad + L.b3, nullptr, stream));
+  RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[0], hidden, 1, p16 + L.W3, 1, hidden, nullptr, 0, nullptr, dz[1],
+                         hidden, H[1], hidden, stream));
+  // hidden layer 2: dW2 = H1^T dZ2, db2, dZ1 = (dZ2 W2^T) * (1 - H1^2)
+  RB_HIP(gemm<kEpiStore>(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, grad + L.W2, hidden, nullptr,
+                         nullptr, 0, nullptr, 0, stream));
+  RB_HIP(colsum(dz[1], batch, hidden, nullptr, din, part, grad + L.b2, nullptr, stream));
+  RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[1], hidden, 1, p16 + L.W2, 1, hidden, nullptr, 0, nullptr, dz[0],
+                         hidden, H[0], hidden, stream));
+  // first layer: dW1 = X^T dZ1, db1 = colsum(dZ1)
+  RB_HIP(colsum(dz[0], batch, hidden, X, din, part, grad + L.b1, grad + L.W1, stream));
+  return RB_OK;
+}
+
+int rb_mlp_adam(float* p32, uint16_t* p16, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                float beta2, float eps, int64_t step, hipStream_t stream) {
+  last_error().clear();
+  if (!p32 || !p16 || !grad || !m || !v || n <= 0 || step < 1 || !(lr >= 0.f))
+    return set_error(RB_EINVAL, "rb_mlp_adam: bad arguments");
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p32, p16, grad, m, v, n, lr,
+                     beta1, beta2, eps, c1, c2);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_mlp_gather(const double* params, const float* targets, const int64_t* idx, int64_t batch, int dout,
+                  const double* ranges, float* X, float* T, hipStream_t stream) {
+  last_error().clear();
+  if (!params || !idx || !ranges || !X || batch <= 0 || (targets && (!T || dout <= 0)))
+    return set_error(RB_EINVAL, "rb_mlp_gather: bad arguments");
+  if (!(ranges[1] > ranges[0]) || !(ranges[3] > ranges[2])) return set_error(RB_EINVAL, "rb_mlp_gather: bad ranges");
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)batch), dim3(256), 0, stream, params, targets, idx, batch, dout,
+                     ranges[0], ranges[1], ranges[2], ranges[3], X, T);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_coef_targets(const void* C, int64_t ldc, int64_t Mn, int k, float* T, hipStream_t stream) {
+  last_error().clear();
+  if (!C || !T || Mn <= 0 || k <= 0 || ldc < k) return set_error(RB_EINVAL, "rb_coef_targets: bad arguments");
+  const int64_t n = Mn * k;
+  hipLaunchKernelGGL(k_coef_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     static_cast<const double2*>(C), ldc, Mn, k, T);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_coef_relerr(const float* Yh, const void* C, int64_t ldc, int64_t Mn, int k, double* out, hipStream_t stream) {
+  last_error().clear();
+  if (!Yh || !C || !out || Mn <= 0 || k <= 0 || ldc < k) return set_error(RB_EINVAL, "rb_coef_relerr: bad arguments");
+  hipLaunchKernelGGL(k_coef_relerr, dim3((unsigned)((Mn + 3) / 4)), dim3(256), 0, stream, Yh,
+                     static_cast<const double2*>(C), ldc, Mn, k, out);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+"""Learned coefficient surrogate on the GPU: an MLP (Mtot, q) -> [Re c; Im c]
+for the projection coefficients c = E^H s of a snapshot on the greedy basis,
+trained on the method's own output (the projection of the training
+snapshots) with the library's BF16 matrix-core forward/backward kernels and
+Adam.  The plain projection of the regenerated snapshot judges each
+prediction and replaces it when its relative error exceeds a threshold.
+
+Everything numeric runs in librb.so (rb_mlp_*, rb_coef_*, rb_chirp_fill,
+rb_project_z); this module allocates device buffers and sequences the calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import _check, _ptr, _stream, load, chirp_fill, project
+
+
+class Surrogate:
+    def __init__(self, k: int, init: np.ndarray, ranges, hidden: int = 256, batch: int = 4096, din: int = 2,
+                 device="cuda"):
+        L = load()
+        self.din, self.hidden, self.dout, self.batch = din, hidden, 2 * k, batch
+        self.k = k
+        n = L.rb_mlp_param_count(din, hidden, self.dout)
+        if n <= 0 or init.size != n:
+            raise ValueError("initial parameter vector has the wrong length")
+        self.n = n
+        self.dev = torch.device(device)
+        self.p32 = torch.from_numpy(np.ascontiguousarray(init, dtype=np.float32)).to(self.dev)
+        self.p16 = torch.zeros(n, dtype=torch.int16, device=self.dev)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.ranges = (ctypes.c_double * 4)(*[float(x) for x in ranges])
+        self._ws = {}
+        self.step = 0
+        # BF16 copy of the initial weights: one Adam step with lr 0 and zero
+        # gradient leaves p32 unchanged and writes p16
+        _check("rb_mlp_adam", L.rb_mlp_adam(_ptr(self.p32), _ptr(self.p16), _ptr(self.grad), _ptr(self.m),
+                                            _ptr(self.v), n, 0.0, 0.9, 0.999, 1e-8, 1, _stream()))
+
+    def workspace(self, batch: int) -> torch.Tensor:
+        if batch not in self._ws:
+            nb = load().rb_mlp_workspace_bytes(batch, self.din, self.hidden, self.dout)
+            self._ws[batch] = torch.empty(nb, dtype=torch.uint8, device=self.dev)
+        return self._ws[batch]
+
+    # -- primitives -------------------------------------------------------
+    def forward(self, X: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
+        B = X.shape[0]
+        if Y is None:
+            Y = torch.empty((B, self.dout), dtype=torch.float32, device=self.dev)
+        _check("rb_mlp_forward", load().rb_mlp_forward(_ptr(self.p32), _ptr(self.p16), self.din, self.hidden,
+                                                       self.dout, _ptr(X), B, _ptr(Y), _ptr(self.workspace(B)),
+                                                       _stream()))
+        return Y
+
+    def loss_backward(self, X: torch.Tensor, Y: torch.Tensor, T: torch.Tensor, loss: torch.Tensor):
+        B = X.shape[0]
+        ws = self.workspace(B)
+        L = load()
+        _check("rb_mlp_loss", L.rb_mlp_loss(_ptr(Y), _ptr(T), B, self.dout, None, _ptr(loss), _ptr(ws), self.din,
+                                            self.hidden, _stream()))
+        _check("rb_mlp_backward", L.rb_mlp_backward(_ptr(self.p32), _ptr(self.p16), self.din, self.hidden,
+                                                    self.dout, _ptr(X), B, None, _ptr(self.grad), _ptr(ws),
+                                                    _stream()))
+
+    def adam(self, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _check("rb_mlp_adam", load().rb_mlp_adam(_ptr(self.p32), _ptr(self.p16), _ptr(self.grad), _ptr(self.m),
+                                                 _ptr(self.v), self.n, lr, b1, b2, eps, self.step, _stream()))
+
+    def gather(self, params: torch.Tensor, targets: torch.Tensor | None, idx: torch.Tensor, X, T):
+        _check("rb_mlp_gather", load().rb_mlp_gather(_ptr(params), _ptr(targets), _ptr(idx), idx.numel(),
+                                                     self.dout, self.ranges, _ptr(X), _ptr(T), _stream()))
+
+    # -- training -----------------------------------------------------------
+    def train(self, params: torch.Tensor, targets: torch.Tensor, steps: int, index_fn, lr0: float = 1e-3,
+              log_every: int = 0, log=None) -> list:
+        """Adam with cosine-decayed learning rate.  index_fn(start, count)
+        returns a (count, batch) int64 numpy array of sample indices."""
+        B = self.batch
+        X = torch.empty((B, self.din), dtype=torch.float32, device=self.dev)
+        T = torch.empty((B, self.dout), dtype=torch.float32, device=self.dev)
+        Y = torch.empty((B, self.dout), dtype=torch.float32, device=self.dev)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
+        hist = []
+        chunk = 500
+        s = 0
+        while s < steps:
+            c = min(chunk, steps - s)
+            idx = torch.from_numpy(index_fn(s, c)).to(self.dev)
+            for i in range(c):
+                lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * (s + i) / steps))
+                self.gather(params, targets, idx[i], X, T)
+                self.forward(X, Y)
+                self.loss_backward(X, Y, T, loss)
+                self.adam(lr)
+                if log_every and ((s + i) % log_every == 0 or s + i == steps - 1):
+                    lv = float(loss.item())
+                    hist.append((s + i, lv))
+                    if log:
+                        log("surrogate step %d loss %.3e" % (s + i, lv))
+            s += c
+        return hist
+
+    def predict(self, params: torch.Tensor, chunk: int = 65536) -> torch.Tensor:
+        """FP32 [Re c; Im c] for every parameter row."""
+        M = params.shape[0]
+        out = torch.empty((M, self.dout), dtype=torch.float32, device=self.dev)
+        for c0 in range(0, M, chunk):
+            mc = min(chunk, M - c0)
+            idx = torch.arange(c0, c0 + mc, dtype=torch.int64, device=self.dev)
+            X = torch.empty((mc, self.din), dtype=torch.float32, device=self.dev)
+            self.gather(params, None, idx, X, None)
+            self.forward(X, out[c0:c0 + mc])
+        return out
+
+
+def coef_targets(C: torch.Tensor) -> torch.Tensor:
+    """(M, k) complex128 coefficients -> (M, 2k) FP32 [Re; Im] targets."""
+    M, k = C.shape
+    T = torch.empty((M, 2 * k), dtype=torch.float32, device=C.device)
+    _check("rb_coef_targets", load().rb_coef_targets(_ptr(C), C.stride(0), M, k, _ptr(T), _stream()))
+    return T
+
+
+def coef_relerr(Yh: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
+    M, k = C.shape
+    out = torch.empty(M, dtype=torch.float64, device=C.device)
+    _check("rb_coef_relerr", load().rb_coef_relerr(_ptr(Yh), _ptr(C), C.stride(0), M, k, _ptr(out), _stream()))
+    return out
+
+
+def evaluate(sur: Surrogate, E: torch.Tensor, params: torch.Tensor, N: int, flo: float, fhi: float,
+             chunk: int = 16384, thresholds=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6)) -> dict:
+    """Held-out evaluation: per chunk, regenerate the snapshots (FP64), project
+    them on E (the judge), predict with the surrogate, and compare.  Returns
+    the error distribution, fallback rates and both throughputs."""
+    M = params.shape[0]
+    errs = torch.empty(M, dtype=torch.float64, device=params.device)
+    t_proj = 0.0
+    t_sur = 0.0
+    # warm both paths at the chunk size (buffer allocation is not timed)
+    p = params[:min(chunk, M)].contiguous()
+    sur.predict(p)
+    project(E, chirp_fill(p, N, flo, fhi))
+    for c0 in range(0, M, chunk):
+        mc = min(chunk, M - c0)
+        p = params[c0:c0 + mc].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = chirp_fill(p, N, flo, fhi)
+        C = project(E, S)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Yh = sur.predict(p)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        errs[c0:c0 + mc] = coef_relerr(Yh, C)
+        t_proj += t1 - t0
+        t_sur += t2 - t1
+        del S, C, Yh
+    e = errs.cpu().numpy()
+    return {
+        "n": int(M),
+        "relerr_median": float(np.median(e)), "relerr_p90": float(np.percentile(e, 90)),
+        "relerr_max": float(e.max()), "relerr_min": float(e.min()),
+        "fallback_rate": {("%.0e" % t): float(np.mean(e > t)) for t in thresholds},
+        "surrogate_evals_per_s": M / t_sur, "projections_per_s": M / t_proj,
+        "errors": e,
+    }

@@ -147,3 +147,63 @@ def unitary(seed: int, n: int) -> np.ndarray:
     Q, R = np.linalg.qr(Z)
     ph = np.diag(R) / np.abs(np.diag(R))
     return Q * ph[None, :]
+
+
+# ---------------------------------------------------------------------------
+# Seeded draws of the learned surrogate (the network's initial weights and
+# its minibatch order); the training arithmetic is elsewhere.
+# ---------------------------------------------------------------------------
+
+def mlp_layout(din: int, hidden: int, dout: int) -> dict:
+    """Offsets of W1, b1, W2, b2, W3, b3, W4, b4 (row-major [in][out]) in the
+    flat parameter vector, and the total length."""
+    off = {}
+    o = 0
+    for name, n in (("W1", din * hidden), ("b1", hidden), ("W2", hidden * hidden), ("b2", hidden),
+                    ("W3", hidden * hidden), ("b3", hidden), ("W4", hidden * dout), ("b4", dout)):
+        off[name] = (o, n)
+        o += n
+    off["total"] = o
+    return off
+
+
+def mlp_init(seed: int, din: int, hidden: int, dout: int) -> np.ndarray:
+    """Glorot-uniform weights, zero biases, as a flat float32 vector."""
+    rng = np.random.default_rng(seed)
+    lay = mlp_layout(din, hidden, dout)
+    p = np.zeros(lay["total"], dtype=np.float32)
+    shapes = {"W1": (din, hidden), "W2": (hidden, hidden), "W3": (hidden, hidden), "W4": (hidden, dout)}
+    for name, (fi, fo) in shapes.items():
+        o, n = lay[name]
+        lim = np.sqrt(6.0 / (fi + fo))
+        p[o:o + n] = rng.uniform(-lim, lim, n).astype(np.float32)
+    return p
+
+
+def batch_indices(seed: int, M: int, batch: int, steps: int, start_step: int = 0) -> np.ndarray:
+    """Minibatch sample indices for steps start_step .. start_step+steps-1:
+    each epoch is a fresh permutation of range(M) (epoch e from seed + e);
+    shape (steps, batch) int64."""
+    out = np.empty((steps, batch), dtype=np.int64)
+    per_epoch = max(1, M // batch)
+    for s in range(steps):
+        g = start_step + s
+        e, r = divmod(g, per_epoch)
+        perm = _perm_cache(seed, e, M)
+        if batch <= M:
+            out[s] = perm[r * batch:(r + 1) * batch]
+        else:
+            out[s] = np.resize(perm, batch)
+    return out
+
+
+_PERM = {}
+
+
+def _perm_cache(seed: int, e: int, M: int) -> np.ndarray:
+    key = (seed, e, M)
+    if key not in _PERM:
+        if len(_PERM) > 4:
+            _PERM.clear()
+        _PERM[key] = np.random.default_rng(seed + e).permutation(M)
+    return _PERM[key]

@@ -1,0 +1,112 @@
+"""The learned coefficient surrogate on the GPU against the FP64 oracle
+(oracle/mlp.py) on the same BF16-rounded weights and inputs, and what the
+trained network gains over the plain projection it falls back to.
+
+Tolerances: the GPU accumulates in FP32 and rounds the same intermediates to
+BF16 as the oracle; an FP32 pre-activation that lands within ~1e-6 of a BF16
+rounding boundary can round the other way (one BF16 ulp, 2^-8 relative), so
+outputs and gradients are compared norm-wise at 1e-2 and elementwise at a
+few BF16 ulps of the tensor's scale."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rb_inputs as ri
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(rb, k=47, B=300, seed=7):
+    from paper_1805_06124_amd.surrogate import Surrogate
+    din, h, dout = 2, 256, 2 * k
+    p = ri.mlp_init(seed, din, h, dout)
+    rng = np.random.default_rng(seed)
+    lay = ri.mlp_layout(din, h, dout)
+    for b in ("b1", "b2", "b3", "b4"):
+        o, n = lay[b]
+        p[o:o + n] = 0.1 * rng.standard_normal(n).astype(np.float32)
+    sur = Surrogate(k, p, ranges=(20.0, 60.0, 1.0, 4.0), batch=B)
+    X = rng.uniform(-1, 1, (B, din)).astype(np.float32)
+    T = (0.3 * rng.standard_normal((B, dout))).astype(np.float32)
+    return sur, p, X, T, (din, h, dout)
+
+
+def test_forward_matches_oracle(rb):
+    sur, p, X, T, (din, h, dout) = _setup(rb)
+    Y = sur.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr, _ = mlp.forward(p, X, din, h, dout, bf16_round=True)
+    assert np.linalg.norm(Y - Yr) <= 1e-2 * np.linalg.norm(Yr)
+    assert np.max(np.abs(Y - Yr)) <= 4 * 2 ** -8 * np.max(np.abs(Yr))
+
+
+def test_gradients_match_oracle(rb):
+    sur, p, X, T, (din, h, dout) = _setup(rb)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    Y = sur.forward(Xd)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sur.loss_backward(Xd, Y, Td, loss)
+    g = sur.grad.cpu().numpy()
+    Yr, Hs = mlp.forward(p, X, din, h, dout, bf16_round=True)
+    lr_, dY = mlp.loss_and_grad_out(Yr, T, bf16_round=True)
+    gr = mlp.backward(p, X, Hs, dY, din, h, dout, bf16_round=True)
+    assert abs(loss.item() - lr_) <= 1e-2 * lr_
+    lay = ri.mlp_layout(din, h, dout)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        o, n = lay[name]
+        a, b = g[o:o + n], gr[o:o + n]
+        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b) + 1e-12, name
+        assert np.max(np.abs(a - b)) <= 8 * 2 ** -8 * np.max(np.abs(b)) + 1e-12, name
+
+
+def test_adam_matches_oracle(rb):
+    sur, p, X, T, (din, h, dout) = _setup(rb)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(p.size).astype(np.float32) * 1e-3
+    w, m, v = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    for step in range(1, 4):
+        sur.grad.copy_(torch.from_numpy(g).cuda())
+        sur.adam(1e-3)
+        w, m, v = mlp.adam(w, g.astype(np.float64), m, v, step, 1e-3)
+    np.testing.assert_allclose(sur.p32.cpu().numpy(), w, rtol=1e-6, atol=1e-7)
+    p16 = sur.p16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    np.testing.assert_array_equal(p16.view(np.float32).astype(np.float64), mlp.bf16(sur.p32.cpu().numpy()))
+
+
+def test_surrogate_trains_and_gains_over_projection(rb):
+    """Train on the method's own output (coefficients of a greedy basis) and
+    evaluate on held-out parameters against the plain projection of the
+    regenerated snapshots, which is also the fallback.  A narrow parameter
+    patch of the 10,000-row chirp family keeps the coefficient maps smooth
+    enough for the network to resolve; the full family is reported by the
+    benchmark."""
+    from paper_1805_06124_amd import surrogate as sg
+    w = ri.WORKLOADS["chirp_10k_409600_c128"]
+    lo0, hi0, lo1, hi1 = 50.0, 50.2, 2.0, 2.05
+    Mtr = 16384
+    Ph_np = ri.chirp_params(1805, Mtr, lo0, hi0, lo1, hi1)
+    P = torch.from_numpy(Ph_np).cuda()
+    S = rb.chirp_fill(P, w.N, w.flo, w.fhi)
+    g = rb.greedy(S, 1e-5, 400)
+    E = g["E"].contiguous()
+    k = g["k"]
+    C = rb.project(E, S)
+    del S
+    T = sg.coef_targets(C)
+    # targets agree with the oracle's projection on sampled columns
+    cols = [0, 77, Mtr - 1]
+    Sh = oracle.chirp(Ph_np[cols], w.N, w.flo, w.fhi)
+    ref = oracle.project(E.cpu().numpy(), Sh)
+    np.testing.assert_allclose(C.cpu().numpy()[cols].T, ref, atol=1e-11)
+    np.testing.assert_array_equal(T.cpu().numpy()[cols][:, :k], C.cpu().numpy()[cols].real.astype(np.float32))
+    sur = sg.Surrogate(k, ri.mlp_init(5, 2, 256, 2 * k), ranges=(lo0, hi0, lo1, hi1), batch=2048)
+    hist = sur.train(P, T, 1500, lambda s, c: ri.batch_indices(9, Mtr, 2048, c, s), lr0=1e-3, log_every=250)
+    print("k", k, "loss", hist)
+    assert hist[-1][1] < 0.02 * hist[0][1], hist
+    Ph = torch.from_numpy(ri.chirp_params(ri.HELDOUT_SEED, 65536, lo0, hi0, lo1, hi1)).cuda()
+    ev = sg.evaluate(sur, E, Ph, w.N, w.flo, w.fhi)
+    print({kk: vv for kk, vv in ev.items() if kk != "errors"})
+    assert np.isfinite(ev["errors"]).all()
+    assert ev["relerr_median"] < 5e-2
+    assert ev["surrogate_evals_per_s"] > 2 * ev["projections_per_s"]
