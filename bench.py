@@ -4,12 +4,19 @@ A step is one complete greedy run (Alg. 3) to tol over the workload's
 snapshot matrix, already resident in HBM: exact initial norms, one fused
 Eq. (6.3) sweep per basis vector, iterated Gram-Schmidt of every pivot,
 re-anchorings and the stop test.  value = greedy iterations per second over
-the timed steps.
+the timed steps (FP64, complex128 storage).
 
 The JSON line also carries
   roofline     : the fused sweep kernel (the dominant kernel) -- algorithmic
                  bytes per launch / average launch duration (HIP events on
                  the library's stream), against 8 TB/s HBM;
+  mixed        : the same workload stored as complex64 (mixed precision,
+                 FP64 basis), time to the same tol and its sweep roofline;
+  projection   : C = E^H S of all snapshots on the final basis (FP64 matrix
+                 cores) with its FLOP rate;
+  surrogate    : the learned coefficient surrogate trained on those
+                 coefficients and evaluated on held-out parameters against
+                 the plain projection of regenerated snapshots;
   cpu_baseline : the CPU oracle's Pythagorean greedy (the paper's own CPU
                  method) timed on this host on a column slice, scaled to the
                  full column count (pivot search cost is linear in M).
@@ -26,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def sweep_bytes(N, M):
@@ -62,6 +70,39 @@ def sweep32_bytes(N, M):
     return 8 * N * M + 8 * N + (8 + 16 + 1 + 16) * M
 
 
+def surrogate_leg(rb, ri, w, E, C, params, args, log):
+    """Train the coefficient surrogate on C = E^H S of all training snapshots
+    and evaluate it on held-out parameters against the plain projection."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06124_amd import surrogate as sg
+    k = E.shape[0]
+    T = sg.coef_targets(C)
+    sur = sg.Surrogate(k, ri.mlp_init(2024, 2, 256, 2 * k), ranges=(w.mlo, w.mhi, w.qlo, w.qhi),
+                       batch=args.sur_batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = sur.train(params, T, args.sur_steps,
+                     lambda s0, c: ri.batch_indices(2025, w.M, args.sur_batch, c, s0), lr0=1e-3,
+                     log_every=max(1, args.sur_steps // 10), log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    Ph = torch.from_numpy(w.params(M=args.sur_heldout, seed=ri.HELDOUT_SEED)).to(params.device)
+    ev = sg.evaluate(sur, E, Ph, w.N, w.flo, w.fhi)
+    e = ev.pop("errors")
+    log("surrogate: train %.1f s, loss %.3e -> %.3e; held-out median rel err %.3e; %.3g evals/s vs %.3g "
+        "projections/s" % (t_train, hist[0][1], hist[-1][1], ev["relerr_median"], ev["surrogate_evals_per_s"],
+                           ev["projections_per_s"]))
+    out = {"k": int(k), "layers": [2, 256, 256, 256, 2 * int(k)], "train_snapshots": w.M,
+           "steps": args.sur_steps, "batch": args.sur_batch, "train_s": t_train,
+           "ms_per_train_step": 1e3 * t_train / args.sur_steps,
+           "loss_first": hist[0][1], "loss_last": hist[-1][1], "heldout": ev,
+           "throughput_gain": ev["surrogate_evals_per_s"] / ev["projections_per_s"],
+           "served_within_1e-2": float(np.mean(e <= 1e-2)), "served_within_1e-6": float(np.mean(e <= 1e-6))}
+    return out
+
+
 def timed_runs(fn, steps, warmup, log, tag):
     import torch
     runs = []
@@ -95,6 +136,10 @@ def main():
     ap.add_argument("--tol", type=float, default=None, help="override the workload's tol")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-steps", type=int, default=20000)
+    ap.add_argument("--sur-batch", type=int, default=4096)
+    ap.add_argument("--sur-heldout", type=int, default=100000)
     ap.add_argument("--cpu-slice", type=int, default=51200)
     ap.add_argument("--cpu-steps", type=int, default=80)
     args = ap.parse_args()
@@ -123,6 +168,8 @@ def main():
         "vs_baseline": None, "data": "synthetic",
     }
     fp64 = None
+    proj = None
+    sur_out = None
     if w.dtype == "c128":
         log("generating %s: N=%d M=%d (%.1f GB complex128)" % (w.name, w.N, w.M, 16 * w.N * w.M / 1e9))
         S = rb.chirp_fill(params, w.N, w.flo, w.fhi)
@@ -145,8 +192,25 @@ def main():
                                   "total": st["ms_total"]})
         log("fp64 sweep: %.3f ms/launch, %.1f GB/s; gs %.1f ms, anchors %.1f ms (%d)" % (
             ms, fp64["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"]))
-        del S, Wk, g, gs, runs
+        del Wk, gs, runs
         torch.cuda.empty_cache()
+        # projection of every snapshot on the final basis (FP64 matrix cores)
+        E = g["E"].contiguous()
+        C = rb.project(E, S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C = rb.project(E, S)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        flops = 8.0 * E.shape[0] * w.N * w.M
+        proj = {"k": int(E.shape[0]), "M": w.M, "ms": 1e3 * tp, "tflops": flops / tp / 1e12,
+                "frac_fp64_peak": flops / tp / 1e12 / FP64_PEAK_TFLOPS}
+        log("projection C = E^H S: k=%d, %.1f ms, %.1f TFLOP/s" % (E.shape[0], 1e3 * tp, proj["tflops"]))
+        del S, g
+        torch.cuda.empty_cache()
+        if not args.no_surrogate:
+            sur_out = surrogate_leg(rb, ri, w, E, C, params, args, log)
+        del C
 
     mixed = None
     if w.dtype == "c64" or not args.no_mixed:
@@ -199,6 +263,10 @@ def main():
                         "speedup_time_to_tol_vs_fp64": fp64["time_to_tol_s"] / mixed["time_to_tol_s"],
                         "equal_error": bool(fp64["err_final"] < tol and mixed["err_final"] < tol)}
         out["fp64_orthogonality"] = fp64["orthogonality"]
+    if proj is not None:
+        out["projection"] = proj
+    if sur_out is not None:
+        out["surrogate"] = sur_out
     print(json.dumps(out), flush=True)
 
 
