@@ -100,14 +100,17 @@ __global__ __launch_bounds__(256) void k_project_z(const double2* __restrict__ E
 
 // ------------------------------------------------------------- residual --
 // Explicit re-anchoring of a block of working columns:
-//   W[:, j] = X[:, j] - E[:, 0:m] C(0:m, j),  nrm[j] = ||W[:, j]||^2 (exact)
+//   W[:, j] = X[:, j] - E[:, 0:m] C(0:m, j),  nrm[j] = ||W[:, j]||^2
 // with C(i, j) = C[i*cI + j*cJ].  X and W may alias (in-place).  The norm is
-// that of the stored W values (after rounding to the output type),
-// accumulated as a double-double and rounded once.
+// that of the stored W values (after rounding to the output type), summed
+// in FP64 (relative error ~ N u of the anchored norm itself, far below what
+// the pivot search resolves).
 //
 // One workgroup owns a strip of 64 columns and walks down all rows in 64-row
 // tiles, so each column's norm is finished inside the workgroup (no partial
-// buffers, deterministic).  The product E C for a row tile runs on FP64
+// buffers, deterministic).  The next chunk of E (and C) is loaded into
+// registers while the matrix cores work on the current one; with m <= 16
+// the C tile is staged once for the whole strip.  The product E C for a row tile runs on FP64
 // matrix cores: 4 waves as 2 x 2, each 32 x 32 = 2 x 2 MFMA 16x16 tiles,
 // the reduction over basis vectors in LDS-staged chunks of 16.
 //   E C, complex:  re = Er Cr - Ei Ci,  im = Er Ci + Ei Cr.
@@ -139,6 +142,7 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
   constexpr int kStage = 2 * kRK * (kRT + 1);
   constexpr int kHalf = (kRT / 2) * (kRT + 1);
   __shared__ double2 smem[kStage > kHalf ? kStage : kHalf];
+  __shared__ double2 sC1[kRK][kRT + 1];  // C tile when m <= kRK (staged once)
   double2 (*sE)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem);
   double2 (*sC)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem + kRK * (kRT + 1));
   double2 (*sD)[kRT + 1] = reinterpret_cast<double2 (*)[kRT + 1]>(smem);
@@ -146,13 +150,50 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int64_t j0 = (int64_t)blockIdx.x * kRT;
+  const bool one_chunk = m <= kRK;
+  constexpr int kQ = (kRT * kRK) / 256;  // staged elements per thread and operand
 
-  // wave w finishes columns j0 + 32 h + 8 w + c (h = 0, 1; c < 8), lane =
-  // row; each row tile's column sums are folded into snorm (one slot per
-  // column, owned by one wave)
-  __shared__ dd snorm[kRT];
-  if (tid < kRT) snorm[tid] = {0.0, 0.0};
+  // staging coordinates of this thread: row r (of the 64), basis index kk
+  int sr[kQ], sk[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int idx = tid + 256 * q;
+    sr[q] = idx % kRT;
+    sk[q] = idx / kRT;
+  }
+  auto load_c = [&](int64_t i0, double2* cv) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int64_t i = i0 + sk[q], j = j0 + sr[q];
+      cv[q] = (i < m && j < M) ? Cc[i * cI + j * cJ] : make_double2(0.0, 0.0);
+    }
+  };
+  auto load_e = [&](int64_t n0, int64_t i0, double2* ev) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int64_t i = i0 + sk[q], n = n0 + sr[q];
+      ev[q] = (i < m && n < N) ? E[n + i * ldE] : make_double2(0.0, 0.0);
+    }
+  };
+  if (one_chunk) {
+    double2 cv[kQ];
+    load_c(0, cv);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) sC1[sk[q]][sr[q]] = cv[q];
+  }
 
+  // per-lane sums of |w|^2 for the columns this wave finishes (plain FP64:
+  // the anchored norms only need to be accurate relative to themselves)
+  double nacc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) nacc[c] = 0.0;
+
+  const int64_t nchunks = (m + kRK - 1) / kRK;
+  double2 ev[kQ], cv[kQ];
+  if (m > 0) {
+    load_e(0, 0, ev);
+    if (!one_chunk) load_c(0, cv);
+  }
   for (int64_t n0 = 0; n0 < N; n0 += kRT) {
     d4v accr[2][2], acci[2][2];
 #pragma unroll
@@ -162,22 +203,27 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
         accr[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
         acci[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
       }
-    for (int64_t i0 = 0; i0 < m; i0 += kRK) {
-      // stage E[n0:n0+64, i0:i0+16] and C(i0:i0+16, j0:j0+64)
+    for (int64_t c = 0; c < nchunks; ++c) {
+      // registers -> LDS, then prefetch the next chunk (or the next row
+      // tile's first chunk) while the matrix cores work
 #pragma unroll
-      for (int q = 0; q < (kRT * kRK) / 256; ++q) {
-        const int idx = tid + 256 * q;
-        const int r = idx % kRT, kk = idx / kRT;
-        const int64_t n = n0 + r, i = i0 + kk, j = j0 + r;
-        double2 ev = make_double2(0.0, 0.0), cv = make_double2(0.0, 0.0);
-        if (i < m) {
-          if (n < N) ev = E[n + i * ldE];
-          if (j < M) cv = Cc[i * cI + j * cJ];
-        }
-        sE[kk][r] = ev;
-        sC[kk][r] = cv;
+      for (int q = 0; q < kQ; ++q) {
+        sE[sk[q]][sr[q]] = ev[q];
+        if (!one_chunk) sC[sk[q]][sr[q]] = cv[q];
       }
       __syncthreads();
+      {
+        int64_t nn = n0, ci = c + 1;
+        if (ci == nchunks) {
+          ci = 0;
+          nn = n0 + kRT;
+        }
+        if (nn < N) {
+          load_e(nn, ci * kRK, ev);
+          if (!one_chunk) load_c(ci * kRK, cv);
+        }
+      }
+      double2 (*sCk)[kRT + 1] = one_chunk ? sC1 : sC;
 #pragma unroll
       for (int kk = 0; kk < kRK; kk += 4) {
         const int r = kk + (lane >> 4);
@@ -185,7 +231,7 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           a[t] = sE[r][wr * 32 + 16 * t + (lane & 15)];
-          b[t] = sC[r][wc * 32 + 16 * t + (lane & 15)];
+          b[t] = sCk[r][wc * 32 + 16 * t + (lane & 15)];
         }
 #pragma unroll
         for (int ta = 0; ta < 2; ++ta)
@@ -201,6 +247,7 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
     }
     // epilogue in two column halves through LDS: W = X - E C, column-wise
     // (lane = row) so every load/store of a wave is one contiguous run
+    const int64_t n = n0 + lane;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (wc == h) {
@@ -214,34 +261,36 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
                   make_double2(accr[ta][tb][r], acci[ta][tb][r]);
       }
       __syncthreads();
-      const int64_t n = n0 + lane;
+      double2 x[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int64_t j = j0 + 32 * h + 8 * wave + c;
+        x[c] = (j < M && n < N) ? ld_x(X + n + j * ldX) : make_double2(0.0, 0.0);
+      }
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int cl = 8 * wave + c;
         const int64_t j = j0 + 32 * h + cl;
-        dd part = {0.0, 0.0};
         if (j < M && n < N) {
           const double2 d = sD[cl][lane];
-          const double2 x = ld_x(X + n + j * ldX);
-          const double2 w = st_w(W + n + j * ldW, x.x - d.x, x.y - d.y);
-          dd_add_sq(part, w.x);
-          dd_add_sq(part, w.y);
+          const double2 w = st_w(W + n + j * ldW, x[c].x - d.x, x[c].y - d.y);
+          nacc[8 * h + c] += w.x * w.x + w.y * w.y;
         }
-        part = wave_dd_sum(part);
-        if (lane == 0) snorm[32 * h + cl] = dd_add(snorm[32 * h + cl], part);
       }
       __syncthreads();
     }
   }
-  if (tid < kRT) {
-    const int64_t j = j0 + tid;
-    if (j < M) {
-      const dd t = snorm[tid];
-      const double r = t.hi + t.lo;
-      nrm[j] = r;
-      if (!__builtin_isfinite(r)) *bad = 1;  // same value from every writer
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double t = wave_sum(nacc[8 * h + c]);
+      const int64_t j = j0 + 32 * h + 8 * wave + c;
+      if (lane == 0 && j < M) {
+        nrm[j] = t;
+        if (!__builtin_isfinite(t)) *bad = 1;  // same value from every writer
+      }
     }
-  }
 }
 
 }  // namespace
