@@ -114,7 +114,7 @@ int rb_project_z(const void* E, int64_t N, int64_t k, int64_t ldE, const void* S
   last_error().clear();
   if (!E || !S || !C || N <= 0 || k <= 0 || M <= 0 || !valid_ld(N, ldE) || !valid_ld(N, ldS) || ldC < k)
     return set_error(RB_EINVAL, "rb_project_z: bad arguments");
-  if ((k + 63) / 64 > 65535) return set_error(RB_EINVAL, "rb_project_z: k too large");
+  if ((k + 159) / 160 > 65535) return set_error(RB_EINVAL, "rb_project_z: k too large");
   RB_HIP(launch_project_z(static_cast<const double2*>(E), N, k, ldE, static_cast<const double2*>(S), M, ldS,
                           static_cast<double2*>(C), ldC, stream));
   RB_HIP(hipStreamSynchronize(stream));

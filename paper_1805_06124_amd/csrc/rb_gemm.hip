@@ -16,68 +16,79 @@ namespace {
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- project --
-// Block tile 64 (basis index i) x 64 (column j), 4 waves as 2 x 2, each wave
-// 32 x 32 = 2 x 2 MFMA tiles.  The reduction runs over rows n in chunks of
-// kKB staged through LDS (E and S chunks, both as complex128 row-major
-// [n][col] so that MFMA operand reads are contiguous).
+// C = E^H S.  A workgroup owns a block of 32*kTA basis vectors (i) x 64
+// columns (j); 4 waves as 2 x 2, each wave 16*kTA x 32 = kTA x 2 MFMA 16x16
+// tiles.  With kTA = 5 a block covers k <= 160, so S is read once.  The
+// reduction runs over rows n in chunks of 16 staged through LDS as
+// [n][col]; the next chunk is loaded into registers while the matrix cores
+// work on the current one.
 //
 // v_mfma_f64_16x16x4f64 operand layout (64 lanes): A(16x4) lane l holds
 // A[l%16][l/16]; B(4x16) lane l holds B[l/16][l%16]; the 16x16 result
 // lane l, register r holds D[l/16 + 4r][l%16].
-constexpr int kPT = 64;  // tile edge (i and j)
-constexpr int kKB = 32;  // rows per LDS chunk
+//   conj(e) s:  re = er sr + ei si,  im = er si - ei sr
+constexpr int kPJ = 64;  // columns per block
+constexpr int kPK = 16;  // rows per LDS chunk
 
+template <int kTA>
 __global__ __launch_bounds__(256) void k_project_z(const double2* __restrict__ E, int64_t N, int64_t k, int64_t ldE,
                                                    const double2* __restrict__ S, int64_t M, int64_t ldS,
                                                    double2* __restrict__ C, int64_t ldC) {
-  // +1 column of padding: the staging writes walk down rows (stride 1 row)
-  __shared__ double2 sE[kKB][kPT + 1];
-  __shared__ double2 sS[kKB][kPT + 1];
+  constexpr int kTI = 32 * kTA;                      // basis vectors per block
+  constexpr int kQE = (kPK * kTI) / 256;             // staged E values per thread
+  constexpr int kQS = (kPK * kPJ) / 256;             // staged S values per thread
+  __shared__ double2 sE[kPK][kTI + 1];
+  __shared__ double2 sS[kPK][kPJ + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t j0 = (int64_t)blockIdx.x * kPT;
-  const int64_t i0 = (int64_t)blockIdx.y * kPT;
-  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int64_t j0 = (int64_t)blockIdx.x * kPJ;
+  const int64_t i0 = (int64_t)blockIdx.y * kTI;
+  const int wi = (wave >> 1) * (16 * kTA), wj = (wave & 1) * 32;
 
-  d4v accr[2][2], acci[2][2];
+  d4v accr[kTA][2], acci[kTA][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < kTA; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       accr[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
       acci[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
     }
-
-  for (int64_t n0 = 0; n0 < N; n0 += kKB) {
-    // stage: thread t loads rows (t % kKB) of columns (t / kKB) + 8 q
+  // thread t stages row (t % 16) of columns t / 16 + 16 q
+  const int rr = tid % kPK, cc = tid / kPK;
+  double2 ev[kQE], sv[kQS];
+  auto load = [&](int64_t n0) {
+    const int64_t n = n0 + rr;
 #pragma unroll
-    for (int q = 0; q < (kKB * kPT) / 256; ++q) {
-      const int idx = tid + 256 * q;
-      const int c = idx / kKB, r = idx % kKB;
-      const int64_t n = n0 + r;
-      double2 ev = make_double2(0.0, 0.0), sv = make_double2(0.0, 0.0);
-      if (n < N) {
-        if (i0 + c < k) ev = E[n + (i0 + c) * ldE];
-        if (j0 + c < M) sv = ld_stream(S + n + (j0 + c) * ldS);
-      }
-      sE[r][c] = ev;
-      sS[r][c] = sv;
+    for (int q = 0; q < kQE; ++q) {
+      const int64_t i = i0 + cc + 16 * q;
+      ev[q] = (n < N && i < k) ? E[n + i * ldE] : make_double2(0.0, 0.0);
     }
+#pragma unroll
+    for (int q = 0; q < kQS; ++q) {
+      const int64_t j = j0 + cc + 16 * q;
+      sv[q] = (n < N && j < M) ? ld_stream(S + n + j * ldS) : make_double2(0.0, 0.0);
+    }
+  };
+  load(0);
+  for (int64_t n0 = 0; n0 < N; n0 += kPK) {
+#pragma unroll
+    for (int q = 0; q < kQE; ++q) sE[rr][cc + 16 * q] = ev[q];
+#pragma unroll
+    for (int q = 0; q < kQS; ++q) sS[rr][cc + 16 * q] = sv[q];
     __syncthreads();
+    if (n0 + kPK < N) load(n0 + kPK);
 #pragma unroll
-    for (int kk = 0; kk < kKB; kk += 4) {
+    for (int kk = 0; kk < kPK; kk += 4) {
       const int r = kk + (lane >> 4);
-      double2 a[2], b[2];
+      double2 a[kTA], b[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = sE[r][wi + 16 * t + (lane & 15)];
-        b[t] = sS[r][wj + 16 * t + (lane & 15)];
-      }
+      for (int t = 0; t < kTA; ++t) a[t] = sE[r][wi + 16 * t + (lane & 15)];
 #pragma unroll
-      for (int ta = 0; ta < 2; ++ta)
+      for (int t = 0; t < 2; ++t) b[t] = sS[r][wj + 16 * t + (lane & 15)];
+#pragma unroll
+      for (int ta = 0; ta < kTA; ++ta)
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb) {
-          // conj(e) * s:  re = er sr + ei si,  im = er si - ei sr
           accr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].x, accr[ta][tb], 0, 0, 0);
           accr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].y, b[tb].y, accr[ta][tb], 0, 0, 0);
           acci[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].y, acci[ta][tb], 0, 0, 0);
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(256) void k_project_z(const double2* __restrict__ E
     __syncthreads();
   }
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < kTA; ++ta)
 #pragma unroll
     for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
@@ -295,13 +306,26 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
 
 }  // namespace
 
+template <int kTA>
+hipError_t launch_project_t(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
+                            int64_t ldS, double2* C, int64_t ldC, hipStream_t s) {
+  dim3 grid((unsigned)((M + kPJ - 1) / kPJ), (unsigned)((k + 32 * kTA - 1) / (32 * kTA)));
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project_z<kTA>, grid, dim3(256), 0, s, E, N, k, ldE, S, M, ldS, C, ldC);
+  return hipGetLastError();
+}
+
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s) {
   if (k <= 0 || M <= 0) return hipSuccess;
-  dim3 grid((unsigned)((M + kPT - 1) / kPT), (unsigned)((k + kPT - 1) / kPT));
-  if (grid.y > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_project_z, grid, dim3(256), 0, s, E, N, k, ldE, S, M, ldS, C, ldC);
-  return hipGetLastError();
+  // smallest block height (32 kTA) that covers k in one block, up to 160
+  switch (k <= 32 ? 1 : k <= 64 ? 2 : k <= 96 ? 3 : k <= 128 ? 4 : 5) {
+    case 1: return launch_project_t<1>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    case 2: return launch_project_t<2>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    case 3: return launch_project_t<3>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    case 4: return launch_project_t<4>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    default: return launch_project_t<5>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+  }
 }
 
 template <class XT, class WT>
