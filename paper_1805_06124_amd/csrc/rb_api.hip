@@ -218,29 +218,50 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
   int status = RB_KMAX;
   err[0] = std::sqrt(A_w > 0.0 ? A_w : 0.0);
 
-  // re-anchoring: X <- X - E[:, a:a+m] C_panel, exact norms, acc = 0
-  auto anchor = [&]() -> int {
+  // Re-anchoring against the m panel vectors a..a+m-1 swept since the last
+  // writing anchoring.  write: X <- X - E_p C_p (the panel restarts);
+  // otherwise only nrm_j <- ||x_j - E_p c_j||^2 (one read of X; the panel
+  // keeps growing: later sweep coefficients of x_j differ from those of the
+  // deflated column by at most u ||x_j|| per vector, an error m u sqrt(A_X)
+  // in err that stays far below the rounding of the explicit form).
+  // Either way acc <- 0 and the pivot is the argmax of the fresh norms.
+  double A_X = A_w;  // largest nrm of X when it was last written
+  auto anchor = [&](bool write) -> int {
     tm.start();
-    if (!W) {
+    if (write && !W) {
       const size_t bytes = sizeof(double2) * (size_t)N * (size_t)M;
       RB_ALLOC(d_Wown, bytes);
       W = d_Wown.as<double2>();
       ldWk = N;
     }
-    // W = X - E[:, a:a+m] C_panel and exact norms of the new columns
-    RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(), stream));
-    X = W;
-    ldX = ldWk;
+    if (write) {
+      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(), stream));
+      X = W;
+      ldX = ldWk;
+    } else {
+      RB_HIP(launch_resid(X, ldX, static_cast<double2*>(nullptr), 0, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm,
+                          d_bad.as<int>(), stream));
+    }
     RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
     RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
     tm.stop(&st.ms_anchor);
-    a = k;
-    m = 0;
+    if (write) {
+      a = k;
+      m = 0;
+      A_X = h_res->v;
+    }
     A_w = h_res->v;
     st.anchors++;
     return RB_OK;
+  };
+  // a norms-only anchoring keeps the extra estimate error 2 m u sqrt(A_X)
+  // rho below a tenth of the resolution threshold theta rho^2
+  auto norms_only_ok = [&](double est) -> bool {
+    if (X == S) return false;
+    const double rho = std::sqrt(est > 0.0 ? est : 0.0);
+    return 2.0 * (double)panel * 0x1p-53 * std::sqrt(A_X) <= 0.1 * o.theta * rho;
   };
 
   while (true) {
@@ -254,7 +275,14 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
     // ---- 1. orthonormalise x_J (iterated Gram-Schmidt, kappa criterion) ----
     tm.start();
     RB_HIP(hipMemcpyAsync(v, X + J * ldX, sizeof(double2) * N, hipMemcpyDeviceToDevice, stream));
-    RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + J, sizeof(double), hipMemcpyDeviceToHost, stream));
+    // ||v|| before the first pass: the stored column (its norm differs from
+    // nrm[J] after a norms-only re-anchoring)
+    if (k > 0) {
+      RB_HIP(launch_sqnorms_small(v, N, 1, N, sq + 1, stream));
+      RB_HIP(hipMemcpyAsync(&h_sc[0], sq + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
+    } else {
+      RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + J, sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
     RB_HIP(hipMemcpyAsync(&h_sc[1], nrm0 + J, sizeof(double), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
     double before = std::sqrt(h_sc[0]);
@@ -295,7 +323,7 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
 
     // ---- 2. fused sweep with the new vector (panel row m) ----
     if (m == panel) {
-      int rc = anchor();
+      int rc = anchor(true);
       if (rc != RB_OK) return rc;
       // the new vector has not been swept yet: the panel restarts at it
       a = k - 1;
@@ -312,7 +340,7 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
 
     // ---- 3. resolution check and error ----
     if (J >= 0 && est_max < o.theta * A_w) {
-      int rc = anchor();
+      int rc = anchor(!norms_only_ok(est_max));
       if (rc != RB_OK) return rc;
       est_max = h_res->v;
       J = h_res->i;

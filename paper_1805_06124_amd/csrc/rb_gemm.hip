@@ -112,8 +112,9 @@ __global__ __launch_bounds__(256) void k_project_z(const double2* __restrict__ E
 // ------------------------------------------------------------- residual --
 // Explicit re-anchoring of a block of working columns:
 //   W[:, j] = X[:, j] - E[:, 0:m] C(0:m, j),  nrm[j] = ||W[:, j]||^2
-// with C(i, j) = C[i*cI + j*cJ].  X and W may alias (in-place).  The norm is
-// that of the stored W values (after rounding to the output type), summed
+// with C(i, j) = C[i*cI + j*cJ].  X and W may alias (in-place); W == NULL
+// computes the norms only.  The norm is that of the stored W values (after
+// rounding to the output type), summed
 // in FP64 (relative error ~ N u of the anchored norm itself, far below what
 // the pivot search resolves).
 //
@@ -284,7 +285,8 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
         const int64_t j = j0 + 32 * h + cl;
         if (j < M && n < N) {
           const double2 d = sD[cl][lane];
-          const double2 w = st_w(W + n + j * ldW, x[c].x - d.x, x[c].y - d.y);
+          double2 w = make_double2(x[c].x - d.x, x[c].y - d.y);
+          if (W) w = st_w(W + n + j * ldW, w.x, w.y);  // W == NULL: norms only
           nacc[8 * h + c] += w.x * w.x + w.y * w.y;
         }
       }

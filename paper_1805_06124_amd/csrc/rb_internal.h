@@ -145,8 +145,8 @@ hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64
 hipError_t launch_scale_into(const double2* v, int64_t N, const double* sq, double2* out, hipStream_t s);
 
 // Re-anchoring: W[:, j] = X[:, j] - sum_{i<m} E[:, i] C(i, j) with
-// C(i, j) = C[i*cI + j*cJ] (X may equal W), nrm[j] = exact ||W[:, j]||^2;
-// *bad set to 1 if a norm is not finite.
+// C(i, j) = C[i*cI + j*cJ] (X may equal W; W == NULL: norms only),
+// nrm[j] = ||W[:, j]||^2; *bad set to 1 if a norm is not finite.
 hipError_t launch_resid(const double2* X, int64_t ldX, double2* W, int64_t ldW, int64_t N, int64_t M,
                         const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
                         double* nrm, int* bad, hipStream_t s);
