@@ -128,7 +128,8 @@ def surrogate_leg(rb, ri, w, E, C, params, args, log):
 def pmc_probe(rb, w, params, log):
     """Kernels for the HBM byte counters: one plain device-to-device copy of
     4 GiB (known traffic: 4 GiB read, 4 GiB written) to calibrate the
-    counters, then three fused sweeps of the workload."""
+    counters, then three fused sweeps of the workload in complex128 and
+    three in complex64."""
     import torch
     n = (4 << 30) // 16
     src = torch.ones(n, dtype=torch.complex128, device=params.device)
@@ -145,6 +146,13 @@ def pmc_probe(rb, w, params, log):
     for i in range(3):
         est, J = rb.sweep(S, e, nrm, acc, None, c)
         log("sweep %d: J=%d est=%.6f bytes=%d" % (i, J, est, sweep_bytes(w.N, w.M)))
+    del S
+    S32 = rb.chirp_fill(params, w.N, w.flo, w.fhi, dtype=torch.complex64)
+    e32 = S32[0].contiguous()
+    acc.zero_()
+    for i in range(3):
+        est, J = rb.sweep_c(S32, e32, nrm, acc, None, c)
+        log("complex64 sweep %d: J=%d bytes=%d" % (i, J[0], sweep32_bytes(w.N, w.M)))
 
 
 def timed_runs(fn, steps, warmup, log, tag):

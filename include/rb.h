@@ -196,12 +196,22 @@ typedef int (*rb_regen_fn)(void *ctx, const int64_t *cols, int64_t n, void *out,
 
 /* Context of the built-in regenerator rb_chirp_regen: the chirp family of
  * rb_chirp_fill with parameters params (device, 2*M doubles), band
- * [flo, fhi] and N rows. */
+ * [flo, fhi] and N rows.  table: device, 3*N doubles prepared by
+ * rb_chirp_table for (flo, fhi, N), or NULL (then every call builds its
+ * own). */
 typedef struct rb_chirp_ctx {
   const double *params;
   double flo, fhi;
   int64_t N;
+  const double *table;
 } rb_chirp_ctx;
+
+/* Row table of the chirp family on N points of [flo, fhi] (all columns
+ * share it): table[3n] = f_n^(-7/6) / ||h||, table[3n+1] = f_n^(-5/3),
+ * table[3n+2] = 1/f_n, where ||h||^2 = sum_n f_n^(-7/3) is every column's
+ * squared norm (the amplitude does not depend on the phase).  Enqueued on
+ * stream (not synchronised). */
+int rb_chirp_table(double flo, double fhi, int64_t N, double *table, hipStream_t stream);
 
 /* rb_regen_fn for the chirp family (ctx is a rb_chirp_ctx*). */
 int rb_chirp_regen(void *ctx, const int64_t *cols, int64_t n, void *out, int64_t ldo, hipStream_t stream);

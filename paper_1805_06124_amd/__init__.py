@@ -46,11 +46,11 @@ class Stats(ctypes.Structure):
 
 class ChirpCtx(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("flo", ctypes.c_double), ("fhi", ctypes.c_double),
-                ("N", ctypes.c_int64)]
+                ("N", ctypes.c_int64), ("table", ctypes.c_void_p)]
 
 
 EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "rb_sweep_z", "rb_greedy_z",
-           "rb_sweep_c", "rb_greedy_c", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
+           "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr"]
 
@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_greedy_c.restype = ctypes.c_int
     L.rb_greedy_c.argtypes = [P, I64, I64, I64, D, I64, P, P, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_chirp_table.restype = ctypes.c_int
+    L.rb_chirp_table.argtypes = [D, D, I64, P, P]
     L.rb_chirp_regen.restype = ctypes.c_int
     L.rb_chirp_regen.argtypes = [P, P, I64, P, I64, P]
     L.rb_project_z.restype = ctypes.c_int
@@ -270,7 +272,9 @@ def greedy_c(S32: torch.Tensor, tol: float, kmax: int, params: torch.Tensor, flo
     else:
         ldW = N
     L = load()
-    ctx = ChirpCtx(params.data_ptr(), float(flo), float(fhi), N)
+    table = torch.empty(3 * N, dtype=torch.float64, device=S32.device)
+    _check("rb_chirp_table", L.rb_chirp_table(float(flo), float(fhi), N, _ptr(table), _stream(stream)))
+    ctx = ChirpCtx(params.data_ptr(), float(flo), float(fhi), N, table.data_ptr())
     fn = ctypes.cast(L.rb_chirp_regen, ctypes.c_void_p)
     rc = L.rb_greedy_c(_ptr(S32), N, M, ld, float(tol), int(kmax), fn, ctypes.cast(ctypes.pointer(ctx), ctypes.c_void_p),
                        _ptr(W), ldW, _ptr(E), N, piv.ctypes.data_as(ctypes.c_void_p),

@@ -127,7 +127,10 @@ int rb_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64
   if (!params || !out || M <= 0 || N <= 0 || !valid_ld(N, ld) || (dtype != 0 && dtype != 1) || !(flo > 0.0) ||
       !(fhi >= flo) || M > 0x7fffffffLL)
     return set_error(RB_EINVAL, "rb_chirp_fill: bad arguments");
-  RB_HIP(launch_chirp_fill(params, nullptr, M, flo, fhi, N, dtype, out, ld, stream));
+  DevBuf tab;
+  RB_ALLOC(tab, sizeof(double) * 3 * (size_t)N);
+  RB_HIP(launch_chirp_table(flo, fhi, N, tab.as<double>(), stream));
+  RB_HIP(launch_chirp_fill(params, nullptr, M, tab.as<double>(), N, dtype, out, ld, stream));
   RB_HIP(hipStreamSynchronize(stream));
   return RB_OK;
 }

@@ -6,8 +6,15 @@
 // with Mtot = total mass (solar masses) * GM_sun/c^3 seconds, on the uniform
 // grid f_n = flo + n (fhi - flo)/(N - 1), divided by its L2 norm.  FP64
 // throughout; complex64 output is the rounded normalised value.
-// One workgroup per column: pass 1 evaluates the column and accumulates its
-// exact squared norm, pass 2 writes the normalised values.
+//
+// Evaluation form.  |h(f_n)| = f_n^(-7/6) does not depend on the phase, so
+// every column has the same norm ||h|| = (sum_n f_n^(-7/3))^(1/2) (computed
+// once, exactly).  With v^2 = (pi Mtot f)^(2/3) the phase separates into a
+// per-column and a per-row factor:
+//   Psi = -pi/4 + A f^(-5/3) + B f^(-1),
+//   A = 3/(128 eta) (pi Mtot)^(-5/3),  B = 3/(128 eta) (3715/756 + 55 eta/9) / (pi Mtot).
+// A row table (f_n^(-7/6)/||h||, f_n^(-5/3), 1/f_n) is built once; each
+// element then costs two FMAs, one sincos and two products, in one pass.
 #include "rb_internal.h"
 
 namespace rb {
@@ -18,77 +25,76 @@ constexpr double kTsun = 4.925490947641267e-6;  // GM_sun / c^3 [s]
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kChirpThreads = 256;
 
-struct ChirpCol {
-  double Mt, eta;
-};
-
-__device__ __forceinline__ double2 chirp_value(const ChirpCol p, double flo, double fhi, int64_t N, int64_t n) {
-#pragma clang fp contract(off)
-  const double f = (N > 1) ? flo + (double)n * (fhi - flo) / (double)(N - 1) : flo;
-  const double v = cbrt(kPi * p.Mt * f);
-  const double v2 = v * v;
-  const double v5 = v2 * v2 * v;
-  const double psi = -kPi / 4.0 + 3.0 / (128.0 * p.eta * v5) * (1.0 + (3715.0 / 756.0 + 55.0 * p.eta / 9.0) * v2);
-  const double amp = pow(f, -7.0 / 6.0);
-  double s, c;
-  sincos(psi, &s, &c);
-  return make_double2(amp * c, -(amp * s));
-}
-
-// Output column j is the snapshot of parameter set pj = cols ? cols[j] : j.
-template <int kDtype>
-__global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restrict__ params,
-                                                         const int64_t* __restrict__ cols, double flo, double fhi,
-                                                         int64_t N, void* __restrict__ out, int64_t ld) {
-  const int64_t j = blockIdx.x;
-  const int64_t pj = cols ? cols[j] : j;
-  ChirpCol p;
-  p.Mt = params[2 * pj] * kTsun;
-  const double q = params[2 * pj + 1];
-  p.eta = q / ((1.0 + q) * (1.0 + q));
+// table[3n] = f^(-7/6) / ||h||, table[3n+1] = f^(-5/3), table[3n+2] = 1/f
+__global__ __launch_bounds__(1024) void k_chirp_table(double flo, double fhi, int64_t N, double* __restrict__ tab) {
   dd acc = {0.0, 0.0};
-  double2* o64 = reinterpret_cast<double2*>(out) + j * ld;
-  float2* o32 = reinterpret_cast<float2*>(out) + j * ld;
-  for (int64_t n = threadIdx.x; n < N; n += kChirpThreads) {
-    const double2 h = chirp_value(p, flo, fhi, N, n);
-    if (kDtype == 0) o64[n] = h;
-    dd_add_sq(acc, h.x);
-    dd_add_sq(acc, h.y);
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
+    const double f = (N > 1) ? flo + (double)n * (fhi - flo) / (double)(N - 1) : flo;
+    const double amp = pow(f, -7.0 / 6.0);
+    tab[3 * n] = amp;
+    tab[3 * n + 1] = pow(f, -5.0 / 3.0);
+    tab[3 * n + 2] = 1.0 / f;
+    dd_add_sq(acc, amp);
   }
   acc = wave_dd_sum(acc);
-  __shared__ dd sh[kChirpThreads / 64];
-  __shared__ double snrm;
+  __shared__ dd sh[16];
+  __shared__ double sinv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) sh[wave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     dd t = sh[0];
-    for (int w = 1; w < kChirpThreads / 64; ++w) t = dd_add(t, sh[w]);
-    snrm = sqrt(t.hi + t.lo);
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) t = dd_add(t, sh[w]);
+    sinv = 1.0 / sqrt(t.hi + t.lo);
   }
   __syncthreads();
-  const double nrm = snrm;
+  const double inv = sinv;
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) tab[3 * n] *= inv;
+}
+
+// Output column j is the snapshot of parameter set pj = cols ? cols[j] : j.
+template <int kDtype>
+__global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restrict__ params,
+                                                         const int64_t* __restrict__ cols,
+                                                         const double* __restrict__ tab, int64_t N,
+                                                         void* __restrict__ out, int64_t ld) {
+  const int64_t j = blockIdx.x;
+  const int64_t pj = cols ? cols[j] : j;
+  const double pm = kPi * params[2 * pj] * kTsun;
+  const double q = params[2 * pj + 1];
+  const double eta = q / ((1.0 + q) * (1.0 + q));
+  const double a0 = 3.0 / (128.0 * eta);
+  const double A = a0 * pow(pm, -5.0 / 3.0);
+  const double B = a0 * (3715.0 / 756.0 + 55.0 * eta / 9.0) / pm;
+  double2* o64 = reinterpret_cast<double2*>(out) + j * ld;
+  float2* o32 = reinterpret_cast<float2*>(out) + j * ld;
   for (int64_t n = threadIdx.x; n < N; n += kChirpThreads) {
-    if (kDtype == 0) {
-      const double2 h = o64[n];
-      o64[n] = make_double2(h.x / nrm, h.y / nrm);
-    } else {
-      const double2 h = chirp_value(p, flo, fhi, N, n);
-      o32[n] = make_float2((float)(h.x / nrm), (float)(h.y / nrm));
-    }
+    const double amp = tab[3 * n];
+    const double psi = -kPi / 4.0 + A * tab[3 * n + 1] + B * tab[3 * n + 2];
+    double s, c;
+    sincos(psi, &s, &c);
+    if (kDtype == 0)
+      o64[n] = make_double2(amp * c, -(amp * s));
+    else
+      o32[n] = make_float2((float)(amp * c), (float)(-(amp * s)));
   }
 }
 
 }  // namespace
 
-hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, double flo, double fhi, int64_t N,
+hipError_t launch_chirp_table(double flo, double fhi, int64_t N, double* table, hipStream_t s) {
+  hipLaunchKernelGGL(k_chirp_table, dim3(1), dim3(1024), 0, s, flo, fhi, N, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, const double* table, int64_t N,
                              int dtype, void* out, int64_t ld, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   if (M > 0x7fffffffLL) return hipErrorInvalidValue;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_chirp<0>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, flo, fhi, N, out, ld);
+    hipLaunchKernelGGL(k_chirp<0>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, table, N, out, ld);
   else
-    hipLaunchKernelGGL(k_chirp<1>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, flo, fhi, N, out, ld);
+    hipLaunchKernelGGL(k_chirp<1>, dim3((unsigned)M), dim3(kChirpThreads), 0, s, params, cols, table, N, out, ld);
   return hipGetLastError();
 }
 

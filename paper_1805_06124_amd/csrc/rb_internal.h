@@ -160,8 +160,10 @@ hipError_t launch_resid(const float2* X, int64_t ldX, float2* W, int64_t ldW, in
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s);
 
+// chirp row table (3 N doubles, see rb_chirp.hip) for launch_chirp_fill
+hipError_t launch_chirp_table(double flo, double fhi, int64_t N, double* table, hipStream_t s);
 // cols (device, may be NULL): output column j uses parameter set cols[j]
-hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, double flo, double fhi, int64_t N,
+hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t M, const double* table, int64_t N,
                              int dtype, void* out, int64_t ld, hipStream_t s);
 
 }  // namespace rb

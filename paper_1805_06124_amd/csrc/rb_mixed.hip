@@ -41,10 +41,25 @@ constexpr double kDelta32 = 2.4e-7;
 
 extern "C" {
 
+int rb_chirp_table(double flo, double fhi, int64_t N, double* table, hipStream_t stream) {
+  last_error().clear();
+  if (!table || N <= 0 || !(flo > 0.0) || !(fhi >= flo)) return set_error(RB_EINVAL, "rb_chirp_table: bad arguments");
+  RB_HIP(launch_chirp_table(flo, fhi, N, table, stream));
+  return RB_OK;
+}
+
 int rb_chirp_regen(void* ctx, const int64_t* cols, int64_t n, void* out, int64_t ldo, hipStream_t stream) {
   const rb_chirp_ctx* c = static_cast<const rb_chirp_ctx*>(ctx);
   if (!c || !c->params || !cols || !out || n <= 0 || c->N <= 0 || ldo < c->N) return RB_EINVAL;
-  hipError_t e = launch_chirp_fill(c->params, cols, n, c->flo, c->fhi, c->N, 0, out, ldo, stream);
+  if (c->table) {
+    hipError_t e = launch_chirp_fill(c->params, cols, n, c->table, c->N, 0, out, ldo, stream);
+    return e == hipSuccess ? 0 : RB_EDEVICE;
+  }
+  DevBuf tab;  // no prepared table: build one for this call
+  if (tab.alloc(sizeof(double) * 3 * (size_t)c->N) != hipSuccess) return RB_ENOMEM;
+  hipError_t e = launch_chirp_table(c->flo, c->fhi, c->N, tab.as<double>(), stream);
+  if (e == hipSuccess) e = launch_chirp_fill(c->params, cols, n, tab.as<double>(), c->N, 0, out, ldo, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the table is freed on return
   return e == hipSuccess ? 0 : RB_EDEVICE;
 }
 

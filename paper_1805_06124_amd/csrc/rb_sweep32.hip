@@ -4,9 +4,10 @@
 // coefficients stay FP64.  Instead of one argmax it keeps the kTop best
 // (est, index) candidates, which the host confirms in FP64.
 //
-// Same work decomposition as the FP64 sweep: a wave owns 4 columns, lane
-// n%64 reads row n (8 B per lane, 512 B contiguous per wave instruction),
-// 8 row blocks in flight per column.
+// Same work decomposition as the FP64 sweep: a wave owns 4 columns and walks
+// down their rows; with 16-byte aligned columns each lane loads two
+// consecutive complex64 values per instruction (1 KiB contiguous per wave
+// instruction), 4 such loads in flight per column.
 #include "rb_internal.h"
 
 namespace rb {
@@ -96,7 +97,12 @@ __device__ __forceinline__ void cmac_conj32(const float2 e, const float2 s, floa
   im += e.x * s.y - e.y * s.x;
 }
 
-template <bool kStoreC>
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// kVec: every lane loads two consecutive complex64 values (16 bytes) per
+// instruction (columns 16-byte aligned); otherwise one (8 bytes).  Either way
+// a row tile is 512 rows, summed in FP32 and added to the FP64 totals.
+template <bool kStoreC, bool kVec>
 __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c(
     const float2* __restrict__ S, int64_t N, int64_t M, int64_t ldS, const float2* __restrict__ e,
     const double* __restrict__ nrm, double* __restrict__ acc, const uint8_t* __restrict__ mask,
@@ -115,24 +121,47 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c(
 #pragma unroll
   for (int c = 0; c < kS32Cols; ++c) re[c] = im[c] = 0.0;
 
-  constexpr int kStep = 64 * kS32Unroll;
+  constexpr int kU = kVec ? kS32Unroll / 2 : kS32Unroll;  // load instructions per column per tile
+  constexpr int kStep = 64 * kS32Unroll;                  // rows per tile (512)
   const int64_t nfull = (N / kStep) * kStep;
   for (int64_t base = 0; base < nfull; base += kStep) {
-    float2 ev[kS32Unroll];
-    float2 sv[kS32Cols][kS32Unroll];
+    if (kVec) {
+      f4v ev[kU], sv[kS32Cols][kU];
 #pragma unroll
-    for (int u = 0; u < kS32Unroll; ++u) ev[u] = e[base + 64 * u + lane];
+      for (int u = 0; u < kU; ++u) ev[u] = *reinterpret_cast<const f4v*>(e + base + 2 * (64 * u + lane));
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c)
+      for (int c = 0; c < kS32Cols; ++c)
 #pragma unroll
-      for (int u = 0; u < kS32Unroll; ++u) sv[c][u] = ld_stream(cp[c] + base + 64 * u + lane);
+        for (int u = 0; u < kU; ++u)
+          sv[c][u] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(cp[c] + base + 2 * (64 * u + lane)));
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c) {
-      float r32 = 0.f, i32 = 0.f;  // FP32 accumulation over this row tile
+      for (int c = 0; c < kS32Cols; ++c) {
+        float r32 = 0.f, i32 = 0.f;  // FP32 accumulation over this row tile
 #pragma unroll
-      for (int u = 0; u < kS32Unroll; ++u) cmac_conj32(ev[u], sv[c][u], r32, i32);
-      re[c] += (double)r32;
-      im[c] += (double)i32;
+        for (int u = 0; u < kU; ++u) {
+          cmac_conj32(make_float2(ev[u].x, ev[u].y), make_float2(sv[c][u].x, sv[c][u].y), r32, i32);
+          cmac_conj32(make_float2(ev[u].z, ev[u].w), make_float2(sv[c][u].z, sv[c][u].w), r32, i32);
+        }
+        re[c] += (double)r32;
+        im[c] += (double)i32;
+      }
+    } else {
+      float2 ev[kU];
+      float2 sv[kS32Cols][kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) ev[u] = e[base + 64 * u + lane];
+#pragma unroll
+      for (int c = 0; c < kS32Cols; ++c)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sv[c][u] = ld_stream(cp[c] + base + 64 * u + lane);
+#pragma unroll
+      for (int c = 0; c < kS32Cols; ++c) {
+        float r32 = 0.f, i32 = 0.f;  // FP32 accumulation over this row tile
+#pragma unroll
+        for (int u = 0; u < kU; ++u) cmac_conj32(ev[u], sv[c][u], r32, i32);
+        re[c] += (double)r32;
+        im[c] += (double)i32;
+      }
     }
   }
   {
@@ -245,12 +274,21 @@ hipError_t launch_sweep_c(const float2* S, int64_t N, int64_t M, int64_t ldS, co
                           int64_t cap, ArgMax* top, hipStream_t s) {
   const int64_t grid = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
   if (grid * kTop + kTop * 256 > cap) return hipErrorInvalidValue;
-  if (c_out)
-    hipLaunchKernelGGL(k_sweep_c<true>, dim3((unsigned)grid), dim3(kS32Waves * 64), 0, s, S, N, M, ldS, e, nrm, acc,
-                       mask, c_out, ldc, partial);
-  else
-    hipLaunchKernelGGL(k_sweep_c<false>, dim3((unsigned)grid), dim3(kS32Waves * 64), 0, s, S, N, M, ldS, e, nrm, acc,
-                       mask, c_out, ldc, partial);
+  const bool vec = (ldS % 2 == 0) && (reinterpret_cast<uintptr_t>(S) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(e) % 16 == 0);
+  const dim3 g((unsigned)grid), b(kS32Waves * 64);
+  if (c_out) {
+    if (vec)
+      hipLaunchKernelGGL((k_sweep_c<true, true>), g, b, 0, s, S, N, M, ldS, e, nrm, acc, mask, c_out, ldc, partial);
+    else
+      hipLaunchKernelGGL((k_sweep_c<true, false>), g, b, 0, s, S, N, M, ldS, e, nrm, acc, mask, c_out, ldc, partial);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_sweep_c<false, true>), g, b, 0, s, S, N, M, ldS, e, nrm, acc, mask, c_out, ldc, partial);
+    else
+      hipLaunchKernelGGL((k_sweep_c<false, false>), g, b, 0, s, S, N, M, ldS, e, nrm, acc, mask, c_out, ldc,
+                         partial);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   return topk_final(partial, grid * kTop, partial + grid * kTop, top, s);
