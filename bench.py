@@ -41,7 +41,8 @@ FP64_PEAK_TFLOPS = 78.6
 # kernel source they were taken on: reported only while that source is
 # unchanged.
 MEASURED_TRAFFIC = {
-    ("k_sweep_z", "chirp_10k_409600_c128"): ("rb_sweep.hip", "1ba593e968bc172a", 65553136835),
+    ("k_sweep_z", "chirp_10k_409600_c128"): ("rb_sweep.hip", "2336c96802028e84", 65554830950),
+    ("k_sweep_c", "chirp_10k_409600_c64"): ("rb_sweep32.hip", "88b8e09ef3e038dc", 32789196151),
 }
 
 

@@ -89,7 +89,7 @@ typedef struct rb_stats {
                           first) */
   int64_t anchors;     /* explicit re-anchorings (all kinds) */
   int64_t gs_passes;   /* Gram-Schmidt passes over all vectors */
-  double ms_sweep;     /* device time in sweeps (collect_stats = 1) */
+  double ms_sweep;     /* device time of the sweep kernels alone (collect_stats = 1) */
   double ms_gs;        /* device time in orthogonalisation (and, mixed
                           precision, candidate confirmation) */
   double ms_anchor;    /* device time in re-anchoring */

@@ -332,10 +332,12 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
       a = k - 1;
     }
     tm.start();
-    RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, res, stream));
+    RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr,
+                          stream));
+    tm.stop(&st.ms_sweep);  // the sweep kernel alone
+    RB_HIP(launch_sweep_final(M, part, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    tm.stop(&st.ms_sweep);
     st.sweeps++;
     ++m;
     double est_max = h_res->v;

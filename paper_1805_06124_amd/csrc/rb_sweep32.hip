@@ -290,7 +290,12 @@ hipError_t launch_sweep_c(const float2* S, int64_t N, int64_t M, int64_t ldS, co
                          partial);
   }
   hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
+  if (err != hipSuccess || !top) return err;
+  return topk_final(partial, grid * kTop, partial + grid * kTop, top, s);
+}
+
+hipError_t launch_sweep_c_final(int64_t M, ArgMax* partial, ArgMax* top, hipStream_t s) {
+  const int64_t grid = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
   return topk_final(partial, grid * kTop, partial + grid * kTop, top, s);
 }
 
