@@ -62,6 +62,9 @@ def lib():
             f.restype = ctypes.c_int
             f.argtypes = [P, I64, I64, I64, D, I64, D, ctypes.c_int, P, I64,
                           P, P, P, P, P, P, P, P]
+        L.oracle_greedy_resume.restype = ctypes.c_int
+        L.oracle_greedy_resume.argtypes = [P, I64, I64, I64, D, I64, D, ctypes.c_int, P, I64, I64,
+                                           P, P, P, P, P, P, P, P]
         L.oracle_project.restype = None
         L.oracle_project.argtypes = [P, I64, I64, I64, P, I64, I64, P, I64]
         L.oracle_residual_norms.restype = None
@@ -116,19 +119,35 @@ def chirp(params, N: int, flo: float, fhi: float) -> np.ndarray:
 
 
 def greedy(S, tol: float, kmax: int, mode: str = "explicit", force=None, kappa: float = 2.0,
-           nu_max: int = 4, want_coeffs: bool = False) -> dict:
+           nu_max: int = 4, want_coeffs: bool = False, E0=None) -> dict:
     """Run the oracle greedy.
 
     mode "explicit": Alg. 2 form (residual matrix), the reference definition.
     mode "pythag"  : pivot search by the Eq. (6.3) update (the paper's code).
-    force          : optional pivot sequence to replay (forced-pivot mode).
-    Returns dict(E (k, N), piv (k,), err (k+1,), rho (k,), nu (k,),
-    pick (k, 2), C (k, M) or None, k, status).
+    force          : optional pivot sequence to replay (forced-pivot mode);
+                     with E0 it lists the pivots of the new steps only.
+    E0             : optional (k0, N) orthonormal basis to continue from
+                     (explicit mode only); kmax counts all k vectors.
+    Returns dict(E (k, N), piv (k - k0,), err (k - k0 + 1,), rho, nu,
+    pick (k - k0, 2), C (k, M) or None, k, k0, status); err[i] is the
+    greedy error with k0 + i vectors.
     """
     S = _cmat(S)
     M, N = S.shape
-    kcap = max(0, min(int(kmax), N, M))
+    k0 = 0
+    if E0 is not None:
+        if mode != "explicit":
+            raise ValueError("a starting basis needs the explicit mode")
+        E0 = _cmat(E0)
+        if E0.shape[1] != N:
+            raise ValueError("E0 and S row counts differ")
+        k0 = E0.shape[0]
+    kcap = max(0, min(int(kmax), N, k0 + M))
+    if kcap < k0:
+        raise ValueError("kmax is below the starting basis size")
     E = np.zeros((max(kcap, 1), N), dtype=np.complex128)
+    if k0:
+        E[:k0] = E0
     piv = np.full(max(kcap, 1), -1, dtype=np.int64)
     err = np.zeros(kcap + 1, dtype=np.float64)
     rho = np.zeros(max(kcap, 1), dtype=np.float64)
@@ -141,17 +160,22 @@ def greedy(S, tol: float, kmax: int, mode: str = "explicit", force=None, kappa: 
         nforce = force.size
     else:
         nforce = 0
-    fn = {"explicit": lib().oracle_greedy_explicit, "pythag": lib().oracle_greedy_pythag}[mode]
-    st = fn(_ptr(S), N, M, N, float(tol), int(kmax), float(kappa), int(nu_max),
-            _ptr(force) if force is not None else None, nforce,
-            _ptr(E), _ptr(piv), _ptr(err), _ptr(rho), _ptr(nu), _ptr(pick),
-            _ptr(C) if C is not None else None, _ptr(kout))
+    fp = _ptr(force) if force is not None else None
+    if k0:
+        st = lib().oracle_greedy_resume(_ptr(S), N, M, N, float(tol), int(kmax), float(kappa), int(nu_max),
+                                        fp, nforce, k0, _ptr(E), _ptr(piv), _ptr(err), _ptr(rho), _ptr(nu),
+                                        _ptr(pick), _ptr(C) if C is not None else None, _ptr(kout))
+    else:
+        fn = {"explicit": lib().oracle_greedy_explicit, "pythag": lib().oracle_greedy_pythag}[mode]
+        st = fn(_ptr(S), N, M, N, float(tol), int(kmax), float(kappa), int(nu_max), fp, nforce,
+                _ptr(E), _ptr(piv), _ptr(err), _ptr(rho), _ptr(nu), _ptr(pick),
+                _ptr(C) if C is not None else None, _ptr(kout))
     if st < 0:
         raise RuntimeError("oracle greedy failed: %s" % STATUS.get(st, st))
     k = int(kout[0])
-    return dict(E=E[:k].copy(), piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(),
-                nu=nu[:k].copy(), pick=pick[:k].copy(),
-                C=(C[:, :k].T.copy() if C is not None else None), k=k, status=STATUS[st])
+    return dict(E=E[:k].copy(), piv=piv[k0:k].copy(), err=err[k0:k + 1].copy(), rho=rho[k0:k].copy(),
+                nu=nu[k0:k].copy(), pick=pick[k0:k].copy(),
+                C=(C[:, :k].T.copy() if C is not None else None), k=k, k0=k0, status=STATUS[st])
 
 
 def project(E, S) -> np.ndarray:
@@ -176,3 +200,36 @@ def residual_norms(E, S) -> np.ndarray:
     out = np.empty(M, dtype=np.float64)
     lib().oracle_residual_norms(_ptr(E) if k else None, N, k, N, _ptr(S), M, N, _ptr(out))
     return out
+
+
+def enrich(E, V, tol: float, kmax: int, kappa: float = 2.0, nu_max: int = 4, force=None) -> dict:
+    """Out-of-sample validation of the basis E (k0, N) on the columns V (Mv, N),
+    then one enrichment (Sec. 6.1): the columns whose explicit residual is
+    >= tol, in index order, continue the greedy from E.
+
+    Residuals shrink as the basis grows, so after the enrichment every column
+    of V, failing or not, is below tol (unless kmax stopped it first).
+
+    Returns dict with:
+    - resid: (Mv,), the residuals against E;
+    - fail: indices into V;
+    - E: (k, N);
+    - piv: pivots as indices into V;
+    - err, rho, nu;
+    - k, k0, status.
+    """
+    E = _cmat(E)
+    V = _cmat(V)
+    r = residual_norms(E, V)
+    fail = np.nonzero(r >= tol)[0]
+    k0 = E.shape[0]
+    if fail.size == 0:
+        return dict(resid=r, fail=fail, E=E.copy(), piv=np.zeros(0, np.int64), err=np.zeros(0),
+                    rho=np.zeros(0), nu=np.zeros(0, np.int32), k=k0, k0=k0, status="OK")
+    f = None
+    if force is not None:
+        pos = {int(c): i for i, c in enumerate(fail)}
+        f = np.array([pos[int(c)] for c in force], dtype=np.int64)
+    g = greedy(V[fail], tol, kmax, kappa=kappa, nu_max=nu_max, E0=E, force=f)
+    return dict(resid=r, fail=fail, E=g["E"], piv=fail[g["piv"]], err=g["err"], rho=g["rho"], nu=g["nu"],
+                pick=g["pick"], k=g["k"], k0=k0, status=g["status"])

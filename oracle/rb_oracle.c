@@ -17,6 +17,9 @@
  *                            Alg. 3, Proposition 5.3), the new basis vector is
  *                            orthonormalised by Hoffmann's iterated MGS
  *                            ("MGSCI", kappa = 2, Sec. 6.1.2).
+ *   - oracle_greedy_resume : the explicit greedy continued from a given
+ *                            orthonormal basis (enrichment after
+ *                            out-of-sample validation, Sec. 6.1).
  *   - oracle_greedy_pythag : the same greedy with the pivot search done by the
  *                            Pythagorean residual update of Eq. (6.3) (stored
  *                            ||s_i||^2 and running sum of |c|^2; no residual
@@ -191,41 +194,65 @@ static int any_nonfinite(const zc *S, int64_t N, int64_t M, int64_t ld) {
  */
 
 /*
- * Alg. 2 / Alg. 3 in explicit residual form.
+ * Alg. 2 / Alg. 3 in explicit residual form, started from k0 >= 0 given
+ * orthonormal basis vectors E[:, 0..k0-1].
+ * k0 = 0 is the greedy itself.  k0 > 0 continues a greedy whose basis
+ * already holds k0 vectors: every column of S is first reduced against
+ * e_1..e_k0 by the same column updates Alg. 2 makes after each pivot (one
+ * MGS step per vector, in order), and the loop then runs from k = k0.  This
+ * is the enrichment step of out-of-sample validation (Sec. 6.1): columns
+ * that fail validation continue the greedy of the existing basis.
  * Stopping rule: continue while err[k] >= tol and k < kmax; return k basis
- * vectors (err[k] < tol, or k = kmax).  If max ||s_j|| < tol no vector is
- * produced.  force_piv (length nforce, may be NULL) replays a given pivot
- * sequence: at step i < nforce the pivot is force_piv[i] instead of the
- * argmax (the argmax and the forced value are both recorded in pick).
+ * vectors in total (err[k] < tol, or k = kmax).  If the largest residual is
+ * already below tol no vector is added.  force_piv (length nforce, may be
+ * NULL) replays a given pivot sequence: at step k0 + i, i < nforce, the pivot
+ * is force_piv[i] instead of the argmax (the argmax and the forced value are
+ * both recorded in pick).  Entries of piv, err, rho, nu, pick below k0 are
+ * left untouched.
  */
-int oracle_greedy_explicit(const zc *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
-                           double kappa, int nu_max, const int64_t *force_piv, int64_t nforce,
+static int greedy_explicit(const zc *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                           double kappa, int nu_max, const int64_t *force_piv, int64_t nforce, int64_t k0,
                            zc *E, int64_t *piv, double *err, double *rho, int *nu, double *pick,
                            zc *C, int64_t *k_out) {
-  if (N <= 0 || M <= 0 || ldS < N || kmax < 0 || !S || !E || !piv || !err || !rho || !k_out) return OR_EINVAL;
+  if (N <= 0 || M <= 0 || ldS < N || kmax < 0 || k0 < 0 || k0 > N || !S || !E || !piv || !err || !rho || !k_out)
+    return OR_EINVAL;
   if (any_nonfinite(S, N, M, ldS)) return OR_ENONFINITE;
   int64_t kcap = kmax;
   if (kcap > N) kcap = N;
-  if (kcap > M) kcap = M;
+  if (kcap > k0 + M) kcap = k0 + M;
+  if (kcap < k0) return OR_EINVAL;
   zc *V = (zc *)malloc(sizeof(zc) * (size_t)N * (size_t)M);
   double *res2 = (double *)malloc(sizeof(double) * (size_t)M);
   unsigned char *mask = (unsigned char *)calloc((size_t)M, 1);
   zc *v = (zc *)malloc(sizeof(zc) * (size_t)N);
   if (!V || !res2 || !mask || !v) { free(V); free(res2); free(mask); free(v); return OR_ENOMEM; }
   for (int64_t j = 0; j < M; ++j) memcpy(V + j * N, S + j * ldS, sizeof(zc) * (size_t)N);
+  /* reduce every column against the k0 given vectors, one MGS step each */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t j = 0; j < M; ++j) {
+    zc *Vj = V + j * N;
+    for (int64_t i = 0; i < k0; ++i) {
+      const zc *ei = E + i * N;
+      zc c = dotc(ei, Vj, N);
+      if (C) C[j * kcap + i] = c;
+      for (int64_t n = 0; n < N; ++n) Vj[n] -= c * ei[n];
+    }
+  }
 
   int status = OR_KMAX;
-  int64_t k = 0;
+  int64_t k = k0;
   oracle_sqnorms(V, N, M, N, res2);
   int64_t p = argmax_unpivoted(res2, mask, M);
-  err[0] = sqrt(res2[p]);
-  if (err[0] < tol) { status = OR_OK; goto done; }
+  err[k0] = sqrt(res2[p]);
+  if (err[k0] < tol) { status = OR_OK; goto done; }
   while (k < kcap) {
     if (err[k] < tol) { status = OR_OK; break; }
     /* pivot: argmax of the explicit residual norms (Alg. 2) */
     int64_t pk = p;
-    if (force_piv && k < nforce) {
-      pk = force_piv[k];
+    if (force_piv && k - k0 < nforce) {
+      pk = force_piv[k - k0];
       if (pk < 0 || pk >= M || mask[pk]) { status = OR_EREPLAY; break; }
     }
     if (pick) { pick[2 * k] = res2[pk]; pick[2 * k + 1] = res2[p]; }
@@ -263,6 +290,24 @@ done:
   *k_out = k;
   free(V); free(res2); free(mask); free(v);
   return status;
+}
+
+int oracle_greedy_explicit(const zc *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                           double kappa, int nu_max, const int64_t *force_piv, int64_t nforce,
+                           zc *E, int64_t *piv, double *err, double *rho, int *nu, double *pick,
+                           zc *C, int64_t *k_out) {
+  return greedy_explicit(S, N, M, ldS, tol, kmax, kappa, nu_max, force_piv, nforce, 0, E, piv, err, rho, nu,
+                         pick, C, k_out);
+}
+
+/* The greedy continued from the k0 orthonormal vectors in E[:, 0..k0-1]
+ * (ld = N); see greedy_explicit. */
+int oracle_greedy_resume(const zc *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                         double kappa, int nu_max, const int64_t *force_piv, int64_t nforce, int64_t k0,
+                         zc *E, int64_t *piv, double *err, double *rho, int *nu, double *pick,
+                         zc *C, int64_t *k_out) {
+  return greedy_explicit(S, N, M, ldS, tol, kmax, kappa, nu_max, force_piv, nforce, k0, E, piv, err, rho, nu,
+                         pick, C, k_out);
 }
 
 /*
