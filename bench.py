@@ -180,6 +180,46 @@ def orthogonality(E):
     return float(torch.linalg.matrix_norm(G - torch.eye(k, dtype=G.dtype, device=G.device), ord=2))
 
 
+def validation_leg(rb, ri, w, E, tol, n_cols, log):
+    """Out-of-sample validation of the final basis on n_cols held-out chirps
+    (seed HELDOUT_SEED, generated on the device in chunks) and one enrichment
+    by the failing columns (rb_enrich_z).  The validation itself is two FP64
+    matrix-core passes per chunk (C = E^H V, then ||V - E C||)."""
+    import torch
+    dev = E.device
+    Pv = torch.from_numpy(w.params(M=n_cols, seed=ri.HELDOUT_SEED)).to(dev)
+    k0 = int(E.shape[0])
+    # warm-up on a slice (allocations, first launches)
+    rb.enrich(E, Pv[:4096].contiguous(), w.flo, w.fhi, tol, w.kmax, 4096, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = rb.enrich(E, Pv, w.flo, w.fhi, tol, w.kmax, n_cols, 1, collect_stats=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the validation pass alone, on a resident chunk of the same columns
+    nres = min(n_cols, 65536)
+    V = rb.chirp_fill(Pv[:nres].contiguous(), w.N, w.flo, w.fhi)
+    rb.residual_norms(E, V)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rb.residual_norms(E, V)
+    torch.cuda.synchronize()
+    tv = time.perf_counter() - t1
+    flops = 2 * 8.0 * k0 * w.N * nres
+    out = {"heldout_cols": n_cols, "seed": ri.HELDOUT_SEED, "k_before": k0, "k_after": int(e["k"]),
+           "n_fail": int(e["n_fail"][0]), "resid_max": float(e["resid_max"][0]), "status": e["status"],
+           "time_s": dt, "cols_per_s": n_cols / dt,
+           "residual_pass": {"cols": nres, "ms": 1e3 * tv, "cols_per_s": nres / tv,
+                             "tflops": flops / tv / 1e12, "frac_fp64_peak": flops / tv / 1e12 / FP64_PEAK_TFLOPS},
+           "enrich_greedy_ms": e["stats"]["ms_sweep"] + e["stats"]["ms_gs"] + e["stats"]["ms_anchor"]}
+    log("validation: %d held-out columns, %d fail (max residual %.3g), k %d -> %d, %.1f ms (%.0f cols/s); "
+        "residual pass %.1f ms per %d cols, %.1f TFLOP/s" % (n_cols, out["n_fail"], out["resid_max"], k0, e["k"],
+                                                               1e3 * dt, out["cols_per_s"], 1e3 * tv, nres,
+                                                               out["residual_pass"]["tflops"]))
+    del V
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +230,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-validation", action="store_true")
+    ap.add_argument("--val-cols", type=int, default=409600)
     ap.add_argument("--sur-steps", type=int, default=20000)
     ap.add_argument("--sur-batch", type=int, default=4096)
     ap.add_argument("--sur-heldout", type=int, default=100000)
@@ -228,6 +270,7 @@ def main():
     fp64 = None
     proj = None
     sur_out = None
+    val_out = None
     if w.dtype == "c128":
         log("generating %s: N=%d M=%d (%.1f GB complex128)" % (w.name, w.N, w.M, 16 * w.N * w.M / 1e9))
         S = rb.chirp_fill(params, w.N, w.flo, w.fhi)
@@ -267,6 +310,9 @@ def main():
         log("projection C = E^H S: k=%d, %.1f ms, %.1f TFLOP/s" % (E.shape[0], 1e3 * tp, proj["tflops"]))
         del S, g
         torch.cuda.empty_cache()
+        if not args.no_validation:
+            val_out = validation_leg(rb, ri, w, E, tol, args.val_cols, log)
+            torch.cuda.empty_cache()
         if not args.no_surrogate:
             sur_out = surrogate_leg(rb, ri, w, E, C, params, args, log)
         del C
@@ -327,6 +373,8 @@ def main():
         out["projection"] = proj
     if sur_out is not None:
         out["surrogate"] = sur_out
+    if val_out is not None:
+        out["validation"] = val_out
     print(json.dumps(out), flush=True)
 
 

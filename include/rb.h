@@ -253,6 +253,81 @@ int rb_project_z(const void *E, int64_t N, int64_t k, int64_t ldE, const void *S
                  void *C, int64_t ldC, hipStream_t stream);
 
 /*
+ * rb_greedy_resume_z -- rb_greedy_z continued from a basis that already
+ * holds k0 orthonormal vectors (the enrichment step of Sec. 6.1: columns
+ * that fail out-of-sample validation continue the greedy of the existing
+ * basis).
+ * Every column of S is first reduced against e_1..e_k0:
+ * X = S - E0 (E0^H S), a block of at most opts->anchor_max vectors at a
+ * time, written to W.  The greedy then runs from k = k0 exactly as in
+ * rb_greedy_z: same pivot rule, orthogonalisation and stopping test, with
+ * err_k = max_j ||s_j - E_k E_k^H s_j||.
+ *   E      device, N x kmax, ldE >= N: columns 0..k0-1 hold the starting
+ *          basis on entry (read); columns k0..k-1 are written
+ *   k0     0 <= k0 <= min(kmax, N); k0 = 0 is rb_greedy_z
+ *   W      as in rb_greedy_z; NULL = allocated (N x M) when k0 > 0
+ *   piv, err, rho, nu  indexed by the basis position: entries k0..k-1
+ *          (err: k0..k) are written, lower entries are left untouched;
+ *          piv holds column indices of S
+ * kmax is clamped to min(N, k0 + M).  Returns as rb_greedy_z.
+ */
+int rb_greedy_resume_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
+                       int64_t ldW, void *E, int64_t ldE, int64_t k0, int64_t *piv, double *err, double *rho,
+                       int32_t *nu, int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
+ * rb_residual_norms_z -- out-of-sample validation (Sec. 6.1): the explicit
+ * residual of every column against the orthonormal basis E,
+ *   out[j] = || v_j - E (E^H v_j) ||_2,
+ * by two FP64 matrix-core passes over V (C = E^H V, then the norms of
+ * V - E C; no Pythagorean shortcut).
+ *   E    device, complex128 N x k, ldE >= N (read); k = 0 gives ||v_j||
+ *   V    device, complex128 N x M, ldV >= N (read)
+ *   out  device, double[M] (written)
+ * Allocates k x min(M, 65536) coefficients of workspace.  Returns
+ * RB_ENONFINITE if a residual is not finite.
+ */
+int rb_residual_norms_z(const void *E, int64_t N, int64_t k, int64_t ldE, const void *V, int64_t M, int64_t ldV,
+                        double *out, hipStream_t stream);
+
+/*
+ * rb_enrich_z -- validation and iterative enrichment of a basis (Sec. 6.1).
+ * Round r (0 <= r < rounds) validates the columns r*Mv .. r*Mv + Mv - 1 of
+ * the regenerator's family against the current basis:
+ *   1. regenerate them in chunks of opts->regen_chunk columns;
+ *   2. take their explicit residuals (as rb_residual_norms_z);
+ *   3. regenerate the columns with residual >= tol (NaN counts as failing),
+ *      in index order;
+ *   4. continue the greedy on them from the current basis
+ *      (rb_greedy_resume_z, overwriting them in place).
+ * Afterwards every column of the round is below tol, unless kmax stopped
+ * the greedy first.
+ *   regen, regen_ctx  column generator (rb_regen_fn); cols are indices into
+ *          its family
+ *   E      device, N x kmax, ldE >= N: columns 0..k_in-1 hold the basis on
+ *          entry; new vectors are appended
+ *   piv    host int64[kmax]: entries k_in..k-1 receive the family index of
+ *          each added vector
+ *   err, rho, nu  as rb_greedy_resume_z, per basis position.  err[i] is the
+ *          largest residual, after i vectors, over the failing columns of
+ *          the round that added vector i (a round's first entry is its
+ *          largest failing residual)
+ *   k_out  host: basis size at the end
+ *   n_fail host int64[rounds]: failing columns per round
+ *   resid_max  host double[rounds]: largest residual of each round,
+ *          against the basis at the round's start
+ *   resid  device double[rounds*Mv]: every residual, or NULL
+ *   stats  NULL or host rb_stats: the continued greedies' totals
+ * Returns RB_OK; RB_KMAX if kmax = min(kmax, N) stopped a round while
+ * columns were still failing; RB_RANK as the greedy does; negative codes on
+ * error.
+ */
+int rb_enrich_z(rb_regen_fn regen, void *regen_ctx, int64_t N, int64_t Mv, int64_t rounds, double tol,
+                int64_t kmax, void *E, int64_t ldE, int64_t k_in, int64_t *piv, double *err, double *rho,
+                int32_t *nu, int64_t *k_out, int64_t *n_fail, double *resid_max, double *resid,
+                const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
  * rb_chirp_fill -- the synthetic snapshot family standing in for the paper's
  * gravitational-wave model (Sec. 6.1.1): column j is the leading-1PN
  * frequency-domain chirp h(f) = f^(-7/6) exp(-i Psi(f)) with

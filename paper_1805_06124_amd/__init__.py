@@ -52,7 +52,8 @@ class ChirpCtx(ctypes.Structure):
 EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "rb_sweep_z", "rb_greedy_z",
            "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
-           "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr"]
+           "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
+           "rb_residual_norms_z", "rb_enrich_z"]
 
 _lib = None
 
@@ -79,6 +80,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_sweep_z.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(I64), P]
     L.rb_greedy_z.restype = ctypes.c_int
     L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
+                              ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_greedy_resume_z.restype = ctypes.c_int
+    L.rb_greedy_resume_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, I64, P, P, P, P, ctypes.POINTER(I64),
+                                     ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_residual_norms_z.restype = ctypes.c_int
+    L.rb_residual_norms_z.argtypes = [P, I64, I64, I64, P, I64, I64, P, P]
+    L.rb_enrich_z.restype = ctypes.c_int
+    L.rb_enrich_z.argtypes = [P, P, I64, I64, I64, D, I64, P, I64, I64, P, P, P, P, ctypes.POINTER(I64), P, P, P,
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_sweep_c.restype = ctypes.c_int
     L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
@@ -190,15 +199,27 @@ def sweep(S: torch.Tensor, e: torch.Tensor, nrm: torch.Tensor, acc: torch.Tensor
     return est.value, J.value
 
 
-def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None, stream=None, **opts) -> dict:
+def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None, stream=None,
+           E0: torch.Tensor | None = None, **opts) -> dict:
     """RB-greedy (Alg. 3) over complex128 S.  W: optional (M, N) working matrix
-    for re-anchoring (may be S itself: S is then overwritten).  Returns dict
-    with E (k, N) complex128 on the GPU, piv, err, rho, nu (numpy), k,
-    status and stats."""
+    for re-anchoring (may be S itself: S is then overwritten).  E0: optional
+    (k0, N) orthonormal basis to continue from (rb_greedy_resume_z); kmax
+    then counts all vectors.  Returns dict with E (k, N) complex128 on the
+    GPU, piv, err, rho, nu (numpy; the k - k0 new steps, err from k0 to k),
+    k, k0, status and stats."""
     import numpy as np
     M, N, ld = _mat(S, torch.complex128)
-    kcap = max(0, min(int(kmax), N, M))
+    k0 = 0
+    if E0 is not None:
+        k0, N0, _ = _mat(E0, torch.complex128)
+        if N0 != N:
+            raise ValueError("E0 and S row counts differ")
+    kcap = max(0, min(int(kmax), N, k0 + M))
+    if kcap < k0:
+        raise ValueError("kmax is below the starting basis size")
     E = torch.empty((max(kcap, 1), N), dtype=torch.complex128, device=S.device)
+    if k0:
+        E[:k0].copy_(E0)
     piv = np.zeros(max(kcap, 1), dtype=np.int64)
     err = np.zeros(kcap + 1, dtype=np.float64)
     rho = np.zeros(max(kcap, 1), dtype=np.float64)
@@ -212,13 +233,78 @@ def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None
             raise ValueError("W must have the shape of S")
     else:
         ldW = N
-    rc = load().rb_greedy_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N,
-                            piv.ctypes.data_as(ctypes.c_void_p), err.ctypes.data_as(ctypes.c_void_p),
-                            rho.ctypes.data_as(ctypes.c_void_p), nu.ctypes.data_as(ctypes.c_void_p),
-                            ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
-    _check("rb_greedy_z", rc, ok=(0, 1, 2))
+    hp = [a.ctypes.data_as(ctypes.c_void_p) for a in (piv, err, rho, nu)]
+    if k0:
+        rc = load().rb_greedy_resume_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N, k0,
+                                       *hp, ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
+        _check("rb_greedy_resume_z", rc, ok=(0, 1, 2))
+    else:
+        rc = load().rb_greedy_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N, *hp,
+                                ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
+        _check("rb_greedy_z", rc, ok=(0, 1, 2))
     k = kout.value
-    return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
+    return dict(E=E[:k], piv=piv[k0:k].copy(), err=err[k0:k + 1].copy(), rho=rho[k0:k].copy(),
+                nu=nu[k0:k].copy(), k=k, k0=k0, status=STATUS[rc], stats=st.as_dict())
+
+
+def residual_norms(E: torch.Tensor, V: torch.Tensor, stream=None) -> torch.Tensor:
+    """Out-of-sample validation: ||v_j - E E^H v_j||_2 for every row v_j of
+    V (M, N) against the orthonormal rows of E (k, N); float64 (M,) on the GPU."""
+    M, N, ldV = _mat(V, torch.complex128)
+    if E is None or E.shape[0] == 0:
+        k, ldE, Ep = 0, N, None
+    else:
+        k, NE, ldE = _mat(E, torch.complex128)
+        if NE != N:
+            raise ValueError("E and V row counts differ")
+        Ep = _ptr(E)
+    out = torch.empty(M, dtype=torch.float64, device=V.device)
+    _check("rb_residual_norms_z", load().rb_residual_norms_z(Ep, N, k, ldE, _ptr(V), M, ldV, _ptr(out),
+                                                             _stream(stream)))
+    return out
+
+
+def enrich(E: torch.Tensor, params: torch.Tensor, flo: float, fhi: float, tol: float, kmax: int, Mv: int,
+           rounds: int = 1, want_resid: bool = False, stream=None, **opts) -> dict:
+    """Validation and iterative enrichment of the basis E (k_in, N) on the
+    chirp family with parameters `params` ((rounds * Mv, 2) float64 on the
+    GPU): round r validates rows r*Mv .. r*Mv + Mv - 1 and continues the
+    greedy on the failing ones.  Returns dict with E (k, N), piv (family
+    indices of the added vectors), err (k_in .. k), rho, nu, n_fail,
+    resid_max (per round), resid ((rounds*Mv,) on the GPU or None), k,
+    k_in, status, stats."""
+    import numpy as np
+    k_in, N, _ = _mat(E, torch.complex128)
+    if (not params.is_cuda or params.dtype != torch.float64 or params.numel() != 2 * Mv * rounds
+            or not params.is_contiguous()):
+        raise ValueError("params must be a contiguous float64 GPU tensor of shape (rounds * Mv, 2)")
+    kcap = max(k_in, min(int(kmax), N))
+    Eb = torch.empty((max(kcap, 1), N), dtype=torch.complex128, device=E.device)
+    Eb[:k_in].copy_(E)
+    piv = np.zeros(max(kcap, 1), dtype=np.int64)
+    err = np.zeros(kcap + 1, dtype=np.float64)
+    rho = np.zeros(max(kcap, 1), dtype=np.float64)
+    nu = np.zeros(max(kcap, 1), dtype=np.int32)
+    n_fail = np.zeros(rounds, dtype=np.int64)
+    rmax = np.zeros(rounds, dtype=np.float64)
+    resid = torch.empty(rounds * Mv, dtype=torch.float64, device=E.device) if want_resid else None
+    kout = ctypes.c_int64()
+    o = default_opts(**opts)
+    st = Stats()
+    L = load()
+    table = torch.empty(3 * N, dtype=torch.float64, device=E.device)
+    _check("rb_chirp_table", L.rb_chirp_table(float(flo), float(fhi), N, _ptr(table), _stream(stream)))
+    ctx = ChirpCtx(params.data_ptr(), float(flo), float(fhi), N, table.data_ptr())
+    fn = ctypes.cast(L.rb_chirp_regen, ctypes.c_void_p)
+    hp = [a.ctypes.data_as(ctypes.c_void_p) for a in (piv, err, rho, nu)]
+    rc = L.rb_enrich_z(fn, ctypes.cast(ctypes.pointer(ctx), ctypes.c_void_p), N, int(Mv), int(rounds), float(tol),
+                       int(kmax), _ptr(Eb), N, k_in, *hp, ctypes.byref(kout), n_fail.ctypes.data_as(ctypes.c_void_p),
+                       rmax.ctypes.data_as(ctypes.c_void_p), _ptr(resid), ctypes.byref(o), ctypes.byref(st),
+                       _stream(stream))
+    _check("rb_enrich_z", rc, ok=(0, 1, 2))
+    k = kout.value
+    return dict(E=Eb[:k], piv=piv[k_in:k].copy(), err=err[k_in:k + 1].copy(), rho=rho[k_in:k].copy(),
+                nu=nu[k_in:k].copy(), n_fail=n_fail, resid_max=rmax, resid=resid, k=k, k_in=k_in,
                 status=STATUS[rc], stats=st.as_dict())
 
 

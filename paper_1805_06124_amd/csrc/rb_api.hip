@@ -16,6 +16,7 @@
 // ||x_j||^2 exactly, acc <- 0.  This is the stored-residual form of the same
 // greedy (the matrix V of Alg. 2, Remark 5.5) entered only when needed; the
 // pivots and errors are those of Alg. 2/3 (Proposition 5.3).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -135,29 +136,40 @@ int rb_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64
   return RB_OK;
 }
 
-int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W_, int64_t ldW,
-                void* E_, int64_t ldE, int64_t* piv, double* err, double* rho, int32_t* nu, int64_t* k_out,
-                const rb_opts* opts_in, rb_stats* stats, hipStream_t stream) {
-  last_error().clear();
+}  // extern "C"
+
+namespace rb {
+
+// The FP64 greedy, started from k0 >= 0 orthonormal vectors already in
+// E[:, 0..k0-1] (k0 = 0: the greedy of Alg. 3 itself).
+int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                  void* W_, int64_t ldW, void* E_, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
+                  int32_t* nu, int64_t* k_out, const rb_opts* opts_in, rb_stats* stats, hipStream_t stream) {
   const auto t_begin = std::chrono::steady_clock::now();
   rb_opts o;
   rb_default_opts(&o);
   if (opts_in) o = *opts_in;
+  char msg[160];
+  auto bad = [&](const char* what) {
+    std::snprintf(msg, sizeof msg, "%s: %s", fn, what);
+    return set_error(RB_EINVAL, msg);
+  };
   if (!S_ || N <= 0 || M <= 0 || !valid_ld(N, ldS) || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol) || !piv ||
-      !err || !rho || !k_out)
-    return set_error(RB_EINVAL, "rb_greedy_z: bad arguments");
-  if (kmax > 0 && (!E_ || !valid_ld(N, ldE))) return set_error(RB_EINVAL, "rb_greedy_z: bad basis buffer");
-  if (W_ && !valid_ld(N, ldW)) return set_error(RB_EINVAL, "rb_greedy_z: bad working-matrix leading dimension");
-  if (W_ == S_ && W_ && ldW != ldS) return set_error(RB_EINVAL, "rb_greedy_z: W == S needs ldW == ldS");
+      !err || !rho || !k_out || k0 < 0)
+    return bad("bad arguments");
+  if ((kmax > 0 || k0 > 0) && (!E_ || !valid_ld(N, ldE))) return bad("bad basis buffer");
+  if (W_ && !valid_ld(N, ldW)) return bad("bad working-matrix leading dimension");
+  if (W_ == S_ && W_ && ldW != ldS) return bad("W == S needs ldW == ldS");
   if (!(o.kappa > 1.0) || o.nu_max < 1 || o.nu_min < 1 || o.nu_min > o.nu_max || !(o.theta > 0.0) ||
       !(o.theta < 1.0) || o.anchor_max < 1)
-    return set_error(RB_EINVAL, "rb_greedy_z: bad options");
+    return bad("bad options");
 
   const double2* S = static_cast<const double2*>(S_);
   double2* E = static_cast<double2*>(E_);
   int64_t kcap = kmax;
   if (kcap > N) kcap = N;
-  if (kcap > M) kcap = M;
+  if (kcap > k0 + M) kcap = k0 + M;
+  if (k0 > kcap) return bad("the starting basis is larger than kmax or N");
   const int64_t panel = o.anchor_max;
   const int64_t np = sweep_partials_needed(M);
 
@@ -206,11 +218,15 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
   RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
   RB_HIP(hipStreamSynchronize(stream));
   tm.stop(&st.ms_anchor);
-  if (*h_bad) return set_error(RB_ENONFINITE, "rb_greedy_z: S holds a non-finite value");
+  if (*h_bad) {
+    std::snprintf(msg, sizeof msg, "%s: S holds a non-finite value", fn);
+    return set_error(RB_ENONFINITE, msg);
+  }
 
   // working matrix X: S until the first anchoring, W afterwards
   const double2* X = S;
   int64_t ldX = ldS;
+  bool written = false;   // X has been written (an anchoring or the start)
   double2* W = static_cast<double2*>(W_);
   int64_t ldWk = ldW;
   double A_w = h_res->v;  // largest nrm since the last anchoring
@@ -219,7 +235,36 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
   int64_t a = 0;          // first basis vector in the coefficient panel
   int64_t m = 0;          // vectors swept since the last anchoring
   int status = RB_KMAX;
-  err[0] = std::sqrt(A_w > 0.0 ? A_w : 0.0);
+
+  // ---- continuation: reduce every column against the k0 given vectors ----
+  // X <- S - E0 (E0^H S), a block at a time (at most `panel` vectors per
+  // block; blocks in order), then nrm = ||x||^2 and the pivot search starts
+  // from there with k = k0.
+  if (k0 > 0) {
+    tm.start();
+    if (!W) {
+      RB_ALLOC(d_Wown, sizeof(double2) * (size_t)N * (size_t)M);
+      W = d_Wown.as<double2>();
+      ldWk = N;
+    }
+    for (int64_t b0 = 0; b0 < k0; b0 += panel) {
+      const int64_t pb = std::min<int64_t>(panel, k0 - b0);
+      RB_HIP(launch_project_z(E + b0 * ldE, N, pb, ldE, X, M, ldX, cpan, pb, stream));
+      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + b0 * ldE, ldE, pb, cpan, 1, pb, nrm, d_bad.as<int>(), stream));
+      X = W;
+      ldX = ldWk;
+    }
+    written = true;
+    RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
+    RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipStreamSynchronize(stream));
+    tm.stop(&st.ms_anchor);
+    st.anchors++;
+    A_w = h_res->v;
+    J = h_res->i;
+    k = a = k0;
+  }
+  err[k] = std::sqrt(A_w > 0.0 ? A_w : 0.0);
 
   // Re-anchoring against the m panel vectors a..a+m-1 swept since the last
   // writing anchoring.  write: X <- X - E_p C_p (the panel restarts);
@@ -241,6 +286,7 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
       RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(), stream));
       X = W;
       ldX = ldWk;
+      written = true;
     } else {
       RB_HIP(launch_resid(X, ldX, static_cast<double2*>(nullptr), 0, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm,
                           d_bad.as<int>(), stream));
@@ -262,7 +308,7 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
   // a norms-only anchoring keeps the extra estimate error 2 m u sqrt(A_X)
   // rho below a tenth of the resolution threshold theta rho^2
   auto norms_only_ok = [&](double est) -> bool {
-    if (X == S) return false;
+    if (!written) return false;
     const double rho = std::sqrt(est > 0.0 ? est : 0.0);
     return 2.0 * (double)panel * 0x1p-53 * std::sqrt(A_X) <= 0.1 * o.theta * rho;
   };
@@ -357,6 +403,26 @@ int rb_greedy_z(const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, i
   st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
   if (stats) *stats = st;
   return status;
+}
+
+}  // namespace rb
+
+extern "C" {
+
+int rb_greedy_z(const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W, int64_t ldW,
+                void* E, int64_t ldE, int64_t* piv, double* err, double* rho, int32_t* nu, int64_t* k_out,
+                const rb_opts* opts, rb_stats* stats, hipStream_t stream) {
+  last_error().clear();
+  return greedy_z_core("rb_greedy_z", S, N, M, ldS, tol, kmax, W, ldW, E, ldE, 0, piv, err, rho, nu, k_out, opts,
+                       stats, stream);
+}
+
+int rb_greedy_resume_z(const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W,
+                       int64_t ldW, void* E, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
+                       int32_t* nu, int64_t* k_out, const rb_opts* opts, rb_stats* stats, hipStream_t stream) {
+  last_error().clear();
+  return greedy_z_core("rb_greedy_resume_z", S, N, M, ldS, tol, kmax, W, ldW, E, ldE, k0, piv, err, rho, nu, k_out,
+                       opts, stats, stream);
 }
 
 }  // extern "C"

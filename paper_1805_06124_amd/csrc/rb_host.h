@@ -14,6 +14,13 @@ namespace rb {
 std::string& last_error();
 int set_error(int code, const char* fmt, ...);
 
+// The FP64 greedy started from k0 >= 0 orthonormal vectors in E[:, 0..k0-1]
+// (rb_greedy_z for k0 = 0, rb_greedy_resume_z otherwise); fn names the entry
+// point in error messages.
+int greedy_z_core(const char* fn, const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
+                  void* W, int64_t ldW, void* E, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
+                  int32_t* nu, int64_t* k_out, const rb_opts* opts, rb_stats* stats, hipStream_t stream);
+
 #define RB_HIP(expr)                                                                                \
   do {                                                                                              \
     hipError_t e_ = (expr);                                                                         \

@@ -85,3 +85,40 @@ def test_mixed_greedy_full_size(rb):
     del W32, S32
     assert g["status"] == "OK" and 100 < g["k"] < w.kmax
     _check_against_oracle(rb, w, P_np, g["E"].contiguous(), g, w.tol, weak=0.9)
+
+
+def test_validation_full_size(rb):
+    """Out-of-sample validation of the full-size FP64 basis on 409,600
+    held-out chirps (seed 1806), plus enrichment.  Checks:
+    - sampled residuals against numpy's explicit residual of the oracle's own
+      columns;
+    - the failing count equals the number of residuals >= tol;
+    - afterwards sampled failing and passing columns are below tol.
+    Device and host generators differ by <= 2e-12 per column, so the residual
+    tolerance is 1e-9 r + 4e-12."""
+    w = ri.WORKLOADS["chirp_10k_409600_c128"]
+    P = torch.from_numpy(w.params()).cuda()
+    S = rb.chirp_fill(P, w.N, w.flo, w.fhi)
+    Wk = torch.empty_like(S)
+    g = rb.greedy(S, w.tol, w.kmax, W=Wk)
+    del S, Wk
+    torch.cuda.empty_cache()
+    E = g["E"].contiguous()
+    Pv_np = w.params(seed=ri.HELDOUT_SEED)
+    e = rb.enrich(E, torch.from_numpy(Pv_np).cuda(), w.flo, w.fhi, w.tol, w.kmax, w.M, 1, want_resid=True)
+    resid = e["resid"].cpu().numpy()
+    assert e["n_fail"][0] == np.count_nonzero(resid >= w.tol)
+    assert e["resid_max"][0] == resid.max()
+    rng = np.random.default_rng(5)
+    cols = rng.choice(w.M, 64, replace=False)
+    V = oracle.chirp(Pv_np[cols], w.N, w.flo, w.fhi)
+    En = E.cpu().numpy()
+    r = np.linalg.norm(V - (V @ En.conj().T) @ En, axis=1)
+    assert np.all(np.abs(resid[cols] - r) <= 1e-9 * r + 4e-12), np.max(np.abs(resid[cols] - r))
+    E2 = e["E"].cpu().numpy()
+    assert np.linalg.norm(E2.conj() @ E2.T - np.eye(e["k"]), 2) <= 2e-13
+    failing = np.nonzero(resid >= w.tol)[0]
+    check = np.concatenate([cols, failing[:64]])
+    V2 = oracle.chirp(Pv_np[check], w.N, w.flo, w.fhi)
+    r2 = np.linalg.norm(V2 - (V2 @ E2.conj().T) @ E2, axis=1)
+    assert r2.max() < w.tol * (1 + 1e-9) + 4e-12, r2.max()

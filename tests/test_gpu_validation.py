@@ -1,0 +1,222 @@
+"""GPU parity of out-of-sample validation and enrichment (Sec. 6.1) against
+the oracle: rb_residual_norms_z, rb_greedy_resume_z (the greedy continued
+from a given basis) and rb_enrich_z (validation rounds plus continuation on
+the failing columns).
+
+Starting bases come from the oracle's own greedy (host), uploaded.  The
+oracle never takes a value produced by the HIP path as input, except the
+pivot sequence it is asked to replay.  Under the replay protocol every
+replayed pivot must lie in the near-tie window of the oracle's own maximum.
+Properties of GPU outputs (certification, orthonormality) are checked with
+numpy.
+
+Tolerances, with u = 2^-53, A = max ||s||^2 and phi_k = 16 (k+1) u sqrt(A):
+- residual norms: |d r| <= 1e-9 r + 64 (k+1) u max||v||.  The GPU takes the
+  projection in blocks on the matrix cores, the oracle vector by vector.
+- greedy continuation: the bounds of the greedy parity tests, indexed by the
+  global basis position.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rb_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check_resume(g, ref, S_host, k0, theta=1e-3, am=128):
+    k = g["k"]
+    n = k - k0
+    A = float(oracle.sqnorms(S_host).max())
+    res = 16 * (am + 1) * U / theta
+    for i in range(n):
+        mine, mx = ref["pick"][i]
+        phi = 16 * (k0 + i + 1) * U * np.sqrt(A)
+        w = mx * (2e-9 + res) + 2 * np.sqrt(max(mx, 0.0)) * phi
+        assert mine >= mx - w, (k0 + i, mine, mx, w)
+    assert ref["k"] == k, (ref["k"], k, g["status"], ref["status"])
+    np.testing.assert_array_equal(ref["piv"], g["piv"])
+    phis = 16 * (np.arange(k0, k + 1) + 1) * U * np.sqrt(A)
+    tol_err = ref["err"] * (1e-10 + res / 2) + phis
+    assert np.all(np.abs(g["err"] - ref["err"]) <= tol_err), np.max(np.abs(g["err"] - ref["err"]) - tol_err)
+    tol_rho = ref["rho"] * 1e-10 + phis[:n]
+    assert np.all(np.abs(g["rho"] - ref["rho"]) <= tol_rho)
+    E = g["E"].cpu().numpy()
+    np.testing.assert_array_equal(E[:k0], ref["E"][:k0])
+    dE = np.linalg.norm(E[k0:] - ref["E"][k0:], axis=1)
+    tol_e = 1e-10 + 64 * (np.arange(k0, k) + 1) * U * np.sqrt(A) / np.maximum(ref["rho"], 1e-300)
+    assert np.all(dE <= tol_e), (np.argmax(dE - tol_e), dE.max())
+    if k:
+        assert np.linalg.norm(E.conj() @ E.T - np.eye(k), 2) <= 2e-13
+
+
+# --------------------------------------------------------------------------
+# validation residuals
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,k,M", [(300, 40, 1037), (257, 1, 63), (64, 17, 5)])
+def test_residual_norms_closed_form(rb, N, k, M):
+    """E = first k columns of a unitary U, V = U [A; B]: residual = ||B_j||
+    (graded over nine decades; several 64-column strips and a ragged tail)."""
+    Uu = ri.unitary(70 + N, N)
+    rng = np.random.default_rng(71)
+    A = rng.standard_normal((k, M)) + 1j * rng.standard_normal((k, M))
+    B = (rng.standard_normal((N - k, M)) + 1j * rng.standard_normal((N - k, M))) * np.logspace(0, -9, M)
+    V = (Uu @ np.vstack([A, B])).T
+    got = rb.residual_norms(_dev(Uu[:, :k].T), _dev(V)).cpu().numpy()
+    want = np.linalg.norm(B, axis=0)
+    vmax = np.linalg.norm(V, axis=1).max()
+    assert np.all(np.abs(got - want) <= 1e-9 * want + 64 * (k + 1) * U * vmax)
+
+
+def test_residual_norms_empty_basis(rb):
+    """k = 0: the residual is the column norm."""
+    V = ri.gaussian(72, 129, 70)
+    got = rb.residual_norms(None, _dev(V)).cpu().numpy()
+    np.testing.assert_allclose(got, np.sqrt(oracle.sqnorms(V)), rtol=1e-14)
+
+
+def test_residual_norms_chirp_parity(rb):
+    """The small chirp family's basis (oracle greedy to 1e-10) validated on
+    2,000 held-out columns (seed 1806): GPU vs oracle, column by column."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S_host = oracle.chirp(w.params(), w.N, w.flo, w.fhi)
+    g = oracle.greedy(S_host, w.tol, w.kmax)
+    V = oracle.chirp(w.params(seed=ri.HELDOUT_SEED), w.N, w.flo, w.fhi)
+    got = rb.residual_norms(_dev(g["E"]), _dev(V)).cpu().numpy()
+    ref = oracle.residual_norms(g["E"], V)
+    assert np.all(np.abs(got - ref) <= 1e-9 * ref + 64 * (g["k"] + 1) * U)
+    assert np.count_nonzero(ref >= w.tol) == np.count_nonzero(got >= w.tol)
+
+
+def test_residual_norms_rejects_bad_arguments(rb):
+    V = _dev(ri.gaussian(73, 32, 8))
+    E = _dev(ri.gaussian(74, 16, 4))
+    with pytest.raises(ValueError):
+        rb.residual_norms(E, V)
+
+
+# --------------------------------------------------------------------------
+# the greedy continued from a given basis
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k1", [1, 37])
+def test_resume_kahan_closed_form(rb, k1):
+    """Kahan's matrix from the first k1 coordinate vectors: pivots k1, k1+1,
+    ... and err_k = (sin theta (1 - delta))^k."""
+    n, theta, delta = 120, 1.2, 0.01
+    S_host = ri.kahan(n, theta, delta)
+    E0 = np.eye(n, dtype=np.complex128)[:k1]
+    g = rb.greedy(_dev(S_host), 0.0, n, E0=_dev(E0))
+    assert g["k0"] == k1
+    kk = g["k"]
+    assert kk > k1 + 40
+    np.testing.assert_array_equal(g["piv"], np.arange(k1, kk))
+    want = (np.sin(theta) * (1 - delta)) ** np.arange(k1, kk)
+    np.testing.assert_allclose(g["err"][:-1], want, rtol=1e-9, atol=64 * n * U)
+    if kk == n:  # every column pivoted: nothing is left to approximate
+        assert g["err"][-1] == 0.0
+
+
+def test_resume_chirp_replay(rb):
+    """The small chirp family continued from the oracle's first 20 vectors,
+    to tol 1e-10; the oracle replays the GPU's pivots from the same start."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S_host = oracle.chirp(w.params(), w.N, w.flo, w.fhi)
+    E0 = oracle.greedy(S_host, w.tol, 20)["E"]
+    g = rb.greedy(_dev(S_host), w.tol, w.kmax, E0=_dev(E0))
+    assert g["status"] == "OK" and g["k"] > 30
+    ref = oracle.greedy(S_host, w.tol, w.kmax, E0=E0, force=g["piv"])
+    _check_resume(g, ref, S_host, 20)
+
+
+def test_resume_multi_block_start(rb):
+    """A 150-vector start (blocks of 128 + 22 in the reduction) on a graded
+    Gaussian 400 x 600 input, continued 50 steps; replayed by the oracle."""
+    S_host = ri.graded(75, 400, 600, 0.995)
+    E0 = oracle.greedy(S_host, 0.0, 150)["E"]
+    g = rb.greedy(_dev(S_host), 0.0, 200, E0=_dev(E0))
+    assert g["k"] == 200 and g["status"] == "KMAX"
+    ref = oracle.greedy(S_host, 0.0, 200, E0=E0, force=g["piv"])
+    _check_resume(g, ref, S_host, 150)
+
+
+def test_resume_already_converged(rb):
+    """A start that already meets tol adds nothing."""
+    S_host = ri.low_rank(76, 90, 50, 5)
+    Q, _ = np.linalg.qr(S_host.T)
+    g = rb.greedy(_dev(S_host), 1e-8, 50, E0=_dev(Q[:, :5].T.copy()))
+    assert g["k"] == 5 and g["status"] == "OK" and g["piv"].size == 0
+    assert g["err"][0] < 1e-12
+
+
+# --------------------------------------------------------------------------
+# validation rounds plus enrichment
+# --------------------------------------------------------------------------
+
+def test_enrich_parity(rb):
+    """The small chirp family's basis validated on two rounds of 1,000
+    held-out columns and enriched by the failing ones.
+    - The failing counts equal the oracle's; no residual lies in the window
+      where rounding could flip a decision.
+    - Each round's new pivots replay in the oracle's enrichment.
+    - At the end every held-out column is below tol (numpy check)."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S_host = oracle.chirp(w.params(), w.N, w.flo, w.fhi)
+    tr = oracle.greedy(S_host, w.tol, w.kmax)
+    Mv, rounds = 1000, 2
+    Pv = w.params(M=Mv * rounds, seed=ri.HELDOUT_SEED)
+    e = rb.enrich(_dev(tr["E"]), _dev(Pv), w.flo, w.fhi, w.tol, w.kmax, Mv, rounds, want_resid=True)
+    assert e["status"] == "OK" and e["k_in"] == tr["k"]
+    resid = e["resid"].cpu().numpy()
+    Eref = tr["E"]
+    k = tr["k"]
+    rho_ref = []
+    for r in range(rounds):
+        V = oracle.chirp(Pv[r * Mv:(r + 1) * Mv], w.N, w.flo, w.fhi)
+        mine = e["piv"][(e["piv"] >= r * Mv) & (e["piv"] < (r + 1) * Mv)] - r * Mv
+        ref = oracle.enrich(Eref, V, w.tol, w.kmax, force=mine)
+        rr = ref["resid"]
+        band = 1e-9 * w.tol + 64 * (k + 1) * U
+        assert not np.any(np.abs(rr - w.tol) <= band)
+        assert e["n_fail"][r] == ref["fail"].size
+        assert np.all(np.abs(resid[r * Mv:(r + 1) * Mv] - rr) <= 1e-9 * rr + 64 * (k + 1) * U)
+        assert abs(e["resid_max"][r] - rr.max()) <= 1e-9 * rr.max() + 64 * (k + 1) * U
+        np.testing.assert_array_equal(ref["piv"], mine)
+        np.testing.assert_allclose(e["rho"][len(rho_ref):len(rho_ref) + ref["rho"].size], ref["rho"],
+                                   rtol=1e-10, atol=64 * (k + ref["rho"].size) * U)
+        rho_ref += list(ref["rho"])
+        Eref = ref["E"]
+        k = ref["k"]
+    assert e["k"] == k
+    E = e["E"].cpu().numpy()
+    assert np.linalg.norm(E.conj() @ E.T - np.eye(e["k"]), 2) <= 2e-13
+    Vall = oracle.chirp(Pv, w.N, w.flo, w.fhi)
+    R = Vall - (Vall @ E.conj().T) @ E
+    assert np.linalg.norm(R, axis=1).max() < w.tol
+    # added vectors: ||d e_i|| <= 1e-10 + 64 (i+1) u / rho_i (their rho are
+    # near tol, so the direction is fixed only to that accuracy)
+    k_in = tr["k"]
+    np.testing.assert_array_equal(E[:k_in], tr["E"])
+    dE = np.linalg.norm(E[k_in:] - Eref[k_in:], axis=1)
+    tol_e = 1e-10 + 64 * (np.arange(k_in, e["k"]) + 1) * U / np.asarray(rho_ref)
+    assert np.all(dE <= tol_e), (dE, tol_e)
+
+
+def test_enrich_nothing_fails(rb):
+    """A loose tolerance: no column fails, the basis is returned unchanged."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S_host = oracle.chirp(w.params(), w.N, w.flo, w.fhi)
+    tr = oracle.greedy(S_host, 1e-6, w.kmax)
+    Pv = w.params(M=500, seed=ri.HELDOUT_SEED)
+    e = rb.enrich(_dev(tr["E"]), _dev(Pv), w.flo, w.fhi, 0.5, w.kmax, 500, 1)
+    assert e["k"] == tr["k"] and e["n_fail"][0] == 0 and e["piv"].size == 0
+    np.testing.assert_array_equal(e["E"].cpu().numpy(), tr["E"])
