@@ -206,17 +206,37 @@ def validation_leg(rb, ri, w, E, tol, n_cols, log):
     torch.cuda.synchronize()
     tv = time.perf_counter() - t1
     flops = 2 * 8.0 * k0 * w.N * nres
+    del V
+    # enrichment at scale: a coarse basis (greedy on the first M/16 training
+    # columns) validated on the same held-out columns and enriched
+    Pc = torch.from_numpy(w.params(M=w.M // 16)).to(dev)
+    Sc = rb.chirp_fill(Pc, w.N, w.flo, w.fhi)
+    gc = rb.greedy(Sc, tol, w.kmax)
+    del Sc
+    torch.cuda.empty_cache()
+    Ec = gc["E"].contiguous()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ec = rb.enrich(Ec, Pv, w.flo, w.fhi, tol, w.kmax, n_cols, 1, collect_stats=1)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t2
+    coarse = {"train_cols": w.M // 16, "k_before": int(gc["k"]), "k_after": int(ec["k"]),
+              "n_fail": int(ec["n_fail"][0]), "resid_max": float(ec["resid_max"][0]), "status": ec["status"],
+              "time_s": dt2, "greedy_ms": ec["stats"]["ms_sweep"] + ec["stats"]["ms_gs"] + ec["stats"]["ms_anchor"]}
+    log("enrichment of a coarse basis (%d training columns): k %d -> %d, %d of %d held-out columns failed "
+        "(max residual %.3g), %.1f ms" % (coarse["train_cols"], gc["k"], ec["k"], coarse["n_fail"], n_cols,
+                                          coarse["resid_max"], 1e3 * dt2))
     out = {"heldout_cols": n_cols, "seed": ri.HELDOUT_SEED, "k_before": k0, "k_after": int(e["k"]),
            "n_fail": int(e["n_fail"][0]), "resid_max": float(e["resid_max"][0]), "status": e["status"],
            "time_s": dt, "cols_per_s": n_cols / dt,
            "residual_pass": {"cols": nres, "ms": 1e3 * tv, "cols_per_s": nres / tv,
                              "tflops": flops / tv / 1e12, "frac_fp64_peak": flops / tv / 1e12 / FP64_PEAK_TFLOPS},
-           "enrich_greedy_ms": e["stats"]["ms_sweep"] + e["stats"]["ms_gs"] + e["stats"]["ms_anchor"]}
+           "enrich_greedy_ms": e["stats"]["ms_sweep"] + e["stats"]["ms_gs"] + e["stats"]["ms_anchor"],
+           "enrich_coarse": coarse}
     log("validation: %d held-out columns, %d fail (max residual %.3g), k %d -> %d, %.1f ms (%.0f cols/s); "
         "residual pass %.1f ms per %d cols, %.1f TFLOP/s" % (n_cols, out["n_fail"], out["resid_max"], k0, e["k"],
                                                                1e3 * dt, out["cols_per_s"], 1e3 * tv, nres,
                                                                out["residual_pass"]["tflops"]))
-    del V
     return out
 
 
@@ -308,6 +328,18 @@ def main():
         proj = {"k": int(E.shape[0]), "M": w.M, "ms": 1e3 * tp, "tflops": flops / tp / 1e12,
                 "frac_fp64_peak": flops / tp / 1e12 / FP64_PEAK_TFLOPS}
         log("projection C = E^H S: k=%d, %.1f ms, %.1f TFLOP/s" % (E.shape[0], 1e3 * tp, proj["tflops"]))
+        # reconstruction (Alg. 4) from the same coefficients, tau2 = tol
+        rec = rb.reconstruct(E, C, tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = rb.reconstruct(E, C, tol)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
+        proj["reconstruction"] = {"tau2": tol, "j": int(E.shape[0]), "k": int(rec["k"]), "ms": 1e3 * tr,
+                                  "sigma_1": float(rec["sigma"][0]), "sigma_j": float(rec["sigma"][-1])}
+        log("reconstruction (Alg. 4): j=%d -> k=%d at tau2=%.0e, sigma %.3g .. %.3g, %.1f ms" % (
+            E.shape[0], rec["k"], tol, rec["sigma"][0], rec["sigma"][-1], 1e3 * tr))
+        del rec
         del S, g
         torch.cuda.empty_cache()
         if not args.no_validation:

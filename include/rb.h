@@ -45,7 +45,8 @@ typedef enum rb_status {
   RB_EINVAL = -1,       /* bad dimensions, pointers or options */
   RB_ENOMEM = -2,       /* device allocation failed */
   RB_EDEVICE = -3,      /* HIP runtime error or no usable device */
-  RB_ENONFINITE = -4    /* S holds a NaN or Inf (or a column norm overflows) */
+  RB_ENONFINITE = -4,   /* S holds a NaN or Inf (or a column norm overflows) */
+  RB_ENOCONV = -5       /* an iterative eigen-solve did not converge */
 } rb_status;
 
 /* Options of the greedy; rb_default_opts() fills the defaults. */
@@ -326,6 +327,35 @@ int rb_enrich_z(rb_regen_fn regen, void *regen_ctx, int64_t N, int64_t Mv, int64
                 int64_t kmax, void *E, int64_t ldE, int64_t k_in, int64_t *piv, double *err, double *rho,
                 int32_t *nu, int64_t *k_out, int64_t *n_fail, double *resid_max, double *resid,
                 const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
+ * rb_reconstruct_z -- the reconstruction algorithm (Alg. 4, Sec. 5.3;
+ * Theorem 5.8).  After a j-term greedy, the coefficients C = E^H S equal
+ * R(1:j, :) up to the column order.  With the SVD C = V Sigma W^H, the
+ * routine keeps k = #{i : sigma_i >= tau2} (so sigma_{k+1} < tau2 <= sigma_k)
+ * and returns X_k = E V(:, 1:k), an N x k orthonormal basis with
+ * ||S - X_k X_k^H S||_2 = sigma_{k+1} whenever S = E C exactly.
+ * The left singular pair is computed on the GPU:
+ *   1. the Gram matrix C C^H;
+ *   2. its Jacobi eigenvectors V0;
+ *   3. a refinement: Jacobi on (V0^H C)(V0^H C)^H gives V1 and the
+ *      eigenvalues, with V = V0 V1.
+ * The singular values then carry an absolute error of a few u sigma_1.
+ *   E      device, complex128 N x j, ldE >= N (read), 1 <= j <= min(N, 2048)
+ *   C      device, complex128 j x M, ldC >= j (read): E^H S
+ *   X      device, complex128 N x j capacity, ldX >= N: columns 0..k-1
+ *          written
+ *   sigma  host double[j]: the singular values of C, non-increasing (out)
+ *   Vout   device, complex128 j x j (ld j): the left singular vectors of C
+ *          in the same order, or NULL (out)
+ *   k_out  host: k (out)
+ * Workspace: about 16 (j M + 5 j^2) bytes plus 32 KB of partial Gram tiles
+ * per (tile pair, split).  Returns RB_ENOCONV if a Jacobi solve does not
+ * settle within 60 sweeps.
+ */
+int rb_reconstruct_z(const void *E, int64_t N, int64_t j, int64_t ldE, const void *C, int64_t M, int64_t ldC,
+                     double tau2, void *X, int64_t ldX, double *sigma, void *Vout, int64_t *k_out,
+                     hipStream_t stream);
 
 /*
  * rb_chirp_fill -- the synthetic snapshot family standing in for the paper's

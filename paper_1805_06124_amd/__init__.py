@@ -20,7 +20,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librb.so")
 
-STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE"}
+STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE",
+          -5: "ENOCONV"}
 
 
 class RBError(RuntimeError):
@@ -53,7 +54,7 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
-           "rb_residual_norms_z", "rb_enrich_z"]
+           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z"]
 
 _lib = None
 
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_enrich_z.restype = ctypes.c_int
     L.rb_enrich_z.argtypes = [P, P, I64, I64, I64, D, I64, P, I64, I64, P, P, P, P, ctypes.POINTER(I64), P, P, P,
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_reconstruct_z.restype = ctypes.c_int
+    L.rb_reconstruct_z.argtypes = [P, I64, I64, I64, P, I64, I64, D, P, I64, P, P, ctypes.POINTER(I64), P]
     L.rb_sweep_c.restype = ctypes.c_int
     L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
     L.rb_greedy_c.restype = ctypes.c_int
@@ -383,6 +386,29 @@ def project(E: torch.Tensor, S: torch.Tensor, stream=None) -> torch.Tensor:
     C = torch.empty((M, k), dtype=torch.complex128, device=S.device)
     _check("rb_project_z", load().rb_project_z(_ptr(E), N, k, ldE, _ptr(S), M, ldS, _ptr(C), k, _stream(stream)))
     return C
+
+
+def reconstruct(E: torch.Tensor, C: torch.Tensor, tau2: float, want_v: bool = False, stream=None) -> dict:
+    """Alg. 4 from the greedy basis E (j, N) and its coefficients C = E^H S
+    as returned by project() ((M, j): row m holds the coefficients of s_m).
+    Returns dict with X ((k, N) complex128 on the GPU, row i = x_{i+1}),
+    sigma (numpy (j,), non-increasing), k, and V ((j, j) on the GPU,
+    column i = left singular vector i of C) if want_v."""
+    import numpy as np
+    j, N, ldE = _mat(E, torch.complex128)
+    M, j2, ldC = _mat(C, torch.complex128)
+    if j2 != j:
+        raise ValueError("C must have one coefficient per basis vector")
+    X = torch.empty((j, N), dtype=torch.complex128, device=E.device)
+    V = torch.empty((j, j), dtype=torch.complex128, device=E.device) if want_v else None
+    sigma = np.zeros(j)
+    kout = ctypes.c_int64()
+    _check("rb_reconstruct_z", load().rb_reconstruct_z(_ptr(E), N, j, ldE, _ptr(C), M, ldC, float(tau2), _ptr(X),
+                                                       N, sigma.ctypes.data_as(ctypes.c_void_p), _ptr(V),
+                                                       ctypes.byref(kout), _stream(stream)))
+    k = kout.value
+    # V was written column-major j x j: the tensor's row i is column i
+    return dict(X=X[:k], sigma=sigma, k=k, V=(V.T if V is not None else None))
 
 
 def chirp_fill(params: torch.Tensor, N: int, flo: float, fhi: float, dtype=torch.complex128,

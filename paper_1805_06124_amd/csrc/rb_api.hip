@@ -71,6 +71,7 @@ const char* rb_strerror(int status) {
     case RB_ENOMEM: return "device allocation failed";
     case RB_EDEVICE: return "HIP runtime error";
     case RB_ENONFINITE: return "non-finite value in S";
+    case RB_ENOCONV: return "an iterative eigen-solve did not converge";
     default: return "unknown status";
   }
 }

@@ -122,3 +122,73 @@ def test_validation_full_size(rb):
     V2 = oracle.chirp(Pv_np[check], w.N, w.flo, w.fhi)
     r2 = np.linalg.norm(V2 - (V2 @ E2.conj().T) @ E2, axis=1)
     assert r2.max() < w.tol * (1 + 1e-9) + 4e-12, r2.max()
+
+
+def test_enrichment_from_coarse_basis_full_size(rb):
+    """A coarse basis, greedy to tol on the first 25,600 training columns
+    only, is validated on the 409,600 held-out chirps and enriched by the
+    columns that fail.  Checks:
+    - the failing count equals the number of residuals >= tol;
+    - the added pivots are failing columns;
+    - sampled residuals against numpy;
+    - afterwards sampled failing and passing columns are below tol;
+    - the basis stays orthonormal."""
+    w = ri.WORKLOADS["chirp_10k_409600_c128"]
+    Pc = torch.from_numpy(w.params(M=25600)).cuda()
+    Sc = rb.chirp_fill(Pc, w.N, w.flo, w.fhi)
+    g = rb.greedy(Sc, w.tol, w.kmax)
+    del Sc
+    E = g["E"].contiguous()
+    Pv_np = w.params(seed=ri.HELDOUT_SEED)
+    e = rb.enrich(E, torch.from_numpy(Pv_np).cuda(), w.flo, w.fhi, w.tol, w.kmax, w.M, 1, want_resid=True)
+    assert e["status"] == "OK"
+    resid = e["resid"].cpu().numpy()
+    failing = np.nonzero(resid >= w.tol)[0]
+    assert e["n_fail"][0] == failing.size > 0
+    assert e["k"] > g["k"]
+    assert set(e["piv"].tolist()) <= set(failing.tolist())
+    rng = np.random.default_rng(6)
+    cols = rng.choice(w.M, 48, replace=False)
+    En = E.cpu().numpy()
+    V = oracle.chirp(Pv_np[cols], w.N, w.flo, w.fhi)
+    r = np.linalg.norm(V - (V @ En.conj().T) @ En, axis=1)
+    assert np.all(np.abs(resid[cols] - r) <= 1e-9 * r + 4e-12), np.max(np.abs(resid[cols] - r))
+    E2 = e["E"].cpu().numpy()
+    assert np.linalg.norm(E2.conj() @ E2.T - np.eye(e["k"]), 2) <= 2e-13
+    check = np.concatenate([cols, rng.choice(failing, min(64, failing.size), replace=False)])
+    V2 = oracle.chirp(Pv_np[check], w.N, w.flo, w.fhi)
+    r2 = np.linalg.norm(V2 - (V2 @ E2.conj().T) @ E2, axis=1)
+    assert r2.max() < w.tol * (1 + 1e-9) + 4e-12, r2.max()
+
+
+def test_reconstruction_full_size(rb):
+    """Alg. 4 on the full-size basis and its coefficients C = E^H S (141 x
+    409,600).  Properties checked with numpy on GPU outputs:
+    - sum sigma_i^2 = ||C||_F^2;
+    - sigma non-increasing;
+    - X_k orthonormal and equal to E V(:, 1:k);
+    - the leading singular values agree with those of a numpy SVD of C
+      (LAPACK on the host copy) to 64 sqrt(j) u sigma_1."""
+    w = ri.WORKLOADS["chirp_10k_409600_c128"]
+    P = torch.from_numpy(w.params()).cuda()
+    S = rb.chirp_fill(P, w.N, w.flo, w.fhi)
+    Wk = torch.empty_like(S)
+    g = rb.greedy(S, w.tol, w.kmax, W=Wk)
+    del Wk
+    E = g["E"].contiguous()
+    C = rb.project(E, S)
+    del S
+    r = rb.reconstruct(E, C, w.tol, want_v=True)
+    j = g["k"]
+    sig = r["sigma"]
+    assert np.all(np.diff(sig) <= 0)
+    Cn = C.cpu().numpy()
+    np.testing.assert_allclose(np.sum(sig ** 2), np.linalg.norm(Cn) ** 2, rtol=1e-12)
+    sv = np.linalg.svd(Cn.T, compute_uv=False)
+    assert np.max(np.abs(sig - sv)) <= 64 * np.sqrt(j) * 2.0 ** -53 * sv[0], np.max(np.abs(sig - sv))
+    k = r["k"]
+    assert k == np.count_nonzero(sv >= w.tol) or np.min(np.abs(sv - w.tol)) <= 64 * np.sqrt(j) * 2.0 ** -53 * sv[0]
+    X = r["X"].cpu().numpy()
+    assert np.linalg.norm(X.conj() @ X.T - np.eye(k), 2) <= 1e-13
+    V = r["V"].cpu().numpy()
+    np.testing.assert_allclose(X, (E.cpu().numpy().T @ V[:, :k]).T, atol=1e-13)
