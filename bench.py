@@ -206,7 +206,26 @@ def validation_leg(rb, ri, w, E, tol, n_cols, log):
     torch.cuda.synchronize()
     tv = time.perf_counter() - t1
     flops = 2 * 8.0 * k0 * w.N * nres
-    del V
+    # empirical-interpolation nodes of the basis, and the interpolant's
+    # errors on the same resident held-out columns
+    rb.eim(E)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ei = rb.eim(E)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t1
+    rb.eim_errors(ei, V)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ie = rb.eim_errors(ei, V)
+    torch.cuda.synchronize()
+    tie = time.perf_counter() - t1
+    eim_out = {"k": int(ei["k"]), "status": ei["status"], "nodes_ms": 1e3 * te,
+               "interp_error_max": float(ie.max()), "interp_error_median": float(ie.median()),
+               "errors_ms": 1e3 * tie, "errors_cols": nres, "errors_cols_per_s": nres / tie}
+    log("EI nodes: k=%d in %.2f ms; interpolant errors on %d held-out columns: max %.3g, median %.3g, %.1f ms" % (
+        ei["k"], 1e3 * te, nres, eim_out["interp_error_max"], eim_out["interp_error_median"], 1e3 * tie))
+    del V, ei, ie
     # enrichment at scale: a coarse basis (greedy on the first M/16 training
     # columns) validated on the same held-out columns and enriched
     Pc = torch.from_numpy(w.params(M=w.M // 16)).to(dev)
@@ -232,7 +251,7 @@ def validation_leg(rb, ri, w, E, tol, n_cols, log):
            "residual_pass": {"cols": nres, "ms": 1e3 * tv, "cols_per_s": nres / tv,
                              "tflops": flops / tv / 1e12, "frac_fp64_peak": flops / tv / 1e12 / FP64_PEAK_TFLOPS},
            "enrich_greedy_ms": e["stats"]["ms_sweep"] + e["stats"]["ms_gs"] + e["stats"]["ms_anchor"],
-           "enrich_coarse": coarse}
+           "enrich_coarse": coarse, "eim": eim_out}
     log("validation: %d held-out columns, %d fail (max residual %.3g), k %d -> %d, %.1f ms (%.0f cols/s); "
         "residual pass %.1f ms per %d cols, %.1f TFLOP/s" % (n_cols, out["n_fail"], out["resid_max"], k0, e["k"],
                                                                1e3 * dt, out["cols_per_s"], 1e3 * tv, nres,

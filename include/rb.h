@@ -358,6 +358,45 @@ int rb_reconstruct_z(const void *E, int64_t N, int64_t j, int64_t ldE, const voi
                      hipStream_t stream);
 
 /*
+ * rb_eim_z -- empirical-interpolation (EI) nodes of the basis e_1..e_k
+ * (Sec. 6.1; the standard discrete empirical interpolation method).
+ * Node p_1 maximises |e_1(n)|.  Node p_j maximises |r_j(n)|, where
+ * r_j = e_j - I_{j-1}[e_j] and I_{j-1} interpolates on e_1..e_{j-1} through
+ * p_1..p_{j-1}.  Ties go to the lowest row.  The residuals are formed by
+ * elimination: r_j = e_j - sum_{i<j} alpha_i r_i, with each r_i stored
+ * divided by r_i(p_i).
+ *   E      device, complex128 N x k, ldE >= N: the basis, linearly
+ *          independent (orthonormal from the greedy) (read)
+ *   nodes  host int64[k]: p_1..p_k, 0-based rows (out)
+ *   peak   host double[k]: |r_j(p_j)|, the pivots of the elimination (out),
+ *          or NULL
+ *   R      device, complex128 N x k (ld N): the normalised residuals
+ *          r_j / r_j(p_j) (out), or NULL (internal)
+ *   Tinv   device, complex128 k x k (ld k): the inverse of the unit lower
+ *          triangular T[l, i] = r_i(p_l) / r_i(p_i) (out), or NULL.
+ *          The empirical interpolant of v is I[v] = R (Tinv v(p)).
+ *   k_out  host: k, or the first j (0-based) with r_j numerically zero,
+ *          max |r_j| <= 64 (j+1) u max |e_j| (a linearly dependent basis,
+ *          status RB_RANK)
+ * Per node: four small kernels, enqueued with no host synchronisation.
+ */
+int rb_eim_z(const void *E, int64_t N, int64_t k, int64_t ldE, int64_t *nodes, double *peak, void *R, void *Tinv,
+             int64_t *k_out, hipStream_t stream);
+
+/*
+ * rb_eim_errors_z -- out-of-sample validation of the empirical interpolant
+ * (Sec. 6.1): out[m] = || v_m - R (Tinv v_m(p)) ||_2 for the M columns of
+ * V.  Each chunk of columns takes:
+ *   1. a gather of the node rows;
+ *   2. Tinv times that gather (matrix cores);
+ *   3. the norms-only residual kernel.
+ *   R, Tinv as written by rb_eim_z; nodes: device int64[k]
+ *   V      device, complex128 N x M, ldV >= N (read);  out: device double[M]
+ */
+int rb_eim_errors_z(const void *R, int64_t N, int64_t k, int64_t ldR, const void *Tinv, const int64_t *nodes,
+                    const void *V, int64_t M, int64_t ldV, double *out, hipStream_t stream);
+
+/*
  * rb_chirp_fill -- the synthetic snapshot family standing in for the paper's
  * gravitational-wave model (Sec. 6.1.1): column j is the leading-1PN
  * frequency-domain chirp h(f) = f^(-7/6) exp(-i Psi(f)) with

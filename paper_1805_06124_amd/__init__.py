@@ -54,7 +54,7 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
-           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z"]
+           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z"]
 
 _lib = None
 
@@ -92,6 +92,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_reconstruct_z.restype = ctypes.c_int
     L.rb_reconstruct_z.argtypes = [P, I64, I64, I64, P, I64, I64, D, P, I64, P, P, ctypes.POINTER(I64), P]
+    L.rb_eim_z.restype = ctypes.c_int
+    L.rb_eim_z.argtypes = [P, I64, I64, I64, P, P, P, P, ctypes.POINTER(I64), P]
+    L.rb_eim_errors_z.restype = ctypes.c_int
+    L.rb_eim_errors_z.argtypes = [P, I64, I64, I64, P, P, P, I64, I64, P, P]
     L.rb_sweep_c.restype = ctypes.c_int
     L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
     L.rb_greedy_c.restype = ctypes.c_int
@@ -409,6 +413,40 @@ def reconstruct(E: torch.Tensor, C: torch.Tensor, tau2: float, want_v: bool = Fa
     k = kout.value
     # V was written column-major j x j: the tensor's row i is column i
     return dict(X=X[:k], sigma=sigma, k=k, V=(V.T if V is not None else None))
+
+
+def eim(E: torch.Tensor, stream=None) -> dict:
+    """Empirical-interpolation nodes of the basis E (k, N).  Returns dict
+    with nodes (numpy int64 (k,)), peak (numpy (k,), |r_j(p_j)|), R ((k, N)
+    on the GPU: row j = r_j / r_j(p_j)), Tinv ((k, k) on the GPU, matrix
+    form) and the interpolant's pieces for eim_errors, k, status."""
+    import numpy as np
+    k, N, ldE = _mat(E, torch.complex128)
+    nodes = np.zeros(k, dtype=np.int64)
+    peak = np.zeros(k)
+    R = torch.empty((k, N), dtype=torch.complex128, device=E.device)
+    Tcm = torch.empty((k, k), dtype=torch.complex128, device=E.device)  # column-major k x k
+    kout = ctypes.c_int64()
+    rc = load().rb_eim_z(_ptr(E), N, k, ldE, nodes.ctypes.data_as(ctypes.c_void_p),
+                         peak.ctypes.data_as(ctypes.c_void_p), _ptr(R), _ptr(Tcm), ctypes.byref(kout),
+                         _stream(stream))
+    _check("rb_eim_z", rc, ok=(0, 2))
+    return dict(nodes=nodes, peak=peak, R=R, Tinv=Tcm.T, _Tcm=Tcm, k=kout.value, status=STATUS[rc])
+
+
+def eim_errors(ei: dict, V: torch.Tensor, stream=None) -> torch.Tensor:
+    """||v - I[v]||_2 for every row v of V (M, N), with the interpolant of
+    eim() (ei); float64 (M,) on the GPU."""
+    R, Tcm = ei["R"], ei["_Tcm"]
+    k, N, ldR = _mat(R, torch.complex128)
+    M, N2, ldV = _mat(V, torch.complex128)
+    if N2 != N:
+        raise ValueError("V and the basis row counts differ")
+    nodes = torch.from_numpy(ei["nodes"]).to(V.device)
+    out = torch.empty(M, dtype=torch.float64, device=V.device)
+    _check("rb_eim_errors_z", load().rb_eim_errors_z(_ptr(R), N, k, ldR, _ptr(Tcm), _ptr(nodes), _ptr(V), M, ldV,
+                                                     _ptr(out), _stream(stream)))
+    return out
 
 
 def chirp_fill(params: torch.Tensor, N: int, flo: float, fhi: float, dtype=torch.complex128,

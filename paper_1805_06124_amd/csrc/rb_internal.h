@@ -137,6 +137,8 @@ hipError_t launch_est_topk(const double* nrm, const double* acc, const uint8_t* 
 int64_t sweep32_partials_needed(int64_t M);
 hipError_t launch_round32(const double2* x, int64_t N, float2* y, hipStream_t s);
 hipError_t launch_iota(int64_t* cols, int64_t start, int64_t n, hipStream_t s);
+// x[i] <- sqrt(x[i]), i < n
+hipError_t launch_sqrt_inplace(double* x, int64_t n, hipStream_t s);
 
 // Gram-Schmidt building blocks over the basis E (N x k, ldE) and nv vectors
 // V (N x nv, ldV):  G = E^H V ;  V -= E G ;  norms.

@@ -92,6 +92,12 @@ __global__ __launch_bounds__(256) void k_fail_scatter(const double* __restrict__
 
 }  // namespace
 
+hipError_t launch_sqrt_inplace(double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sqrt_inplace, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+
 // out[j] = ||v_j - E (E^H v_j)||^2 for the M columns of V, in chunks of at
 // most `chunk` columns; Cw holds k x chunk coefficients.
 static hipError_t residual_sq(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* V, int64_t M,
@@ -126,8 +132,7 @@ int rb_residual_norms_z(const void* E_, int64_t N, int64_t k, int64_t ldE, const
   RB_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), stream));
   RB_HIP(residual_sq(static_cast<const double2*>(E_), N, k, ldE, static_cast<const double2*>(V_), M, ldV, out,
                      Cw.as<double2>(), chunk, bad.as<int>(), stream));
-  hipLaunchKernelGGL(k_sqrt_inplace, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream, out, M);
-  RB_HIP(hipGetLastError());
+  RB_HIP(launch_sqrt_inplace(out, M, stream));
   int hbad = 0;
   RB_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
   RB_HIP(hipStreamSynchronize(stream));
@@ -178,8 +183,7 @@ int rb_enrich_z(rb_regen_fn regen, void* regen_ctx, int64_t N, int64_t Mv, int64
       RB_HIP(residual_sq(E, N, k, ldE, Vc.as<double2>(), mc, N, r + j0, Cw.as<double2>(), mc, d_bad.as<int>(),
                          stream));
     }
-    hipLaunchKernelGGL(k_sqrt_inplace, dim3((unsigned)nb), dim3(256), 0, stream, r, Mv);
-    RB_HIP(hipGetLastError());
+    RB_HIP(launch_sqrt_inplace(r, Mv, stream));
     if (resid) RB_HIP(hipMemcpyAsync(resid + base, r, sizeof(double) * Mv, hipMemcpyDeviceToDevice, stream));
     // ---- 2. the failing columns, in index order ----
     hipLaunchKernelGGL(k_fail_count, dim3((unsigned)nb), dim3(256), 0, stream, r, Mv, tol, d_cnt.as<int>());
