@@ -14,6 +14,7 @@ namespace rb {
 namespace {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- project --
 // C = E^H S.  A workgroup owns a block of 32*kTA basis vectors (i) x 64
@@ -144,7 +145,10 @@ __device__ __forceinline__ double2 st_w(float2* p, double re, double im) {
   return make_double2((double)v.x, (double)v.y);
 }
 
-template <class XT, class WT>
+// kVec (complex64 X only): the epilogue moves two consecutive rows per lane
+// with 16-byte accesses (X, and W when written, 16-byte aligned with even
+// leading dimensions); otherwise one row per lane.
+template <class XT, class WT, bool kVec>
 __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, int64_t ldW, int64_t N, int64_t M,
                                                const double2* __restrict__ E, int64_t ldE, int64_t m,
                                                const double2* __restrict__ Cc, int64_t cI, int64_t cJ,
@@ -236,8 +240,12 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
         }
       }
       double2 (*sCk)[kRT + 1] = one_chunk ? sC1 : sC;
+      // basis vectors present in this chunk: the steps of 4 beyond them
+      // would only add zero products
+      const int64_t kval = m - c * kRK;
 #pragma unroll
       for (int kk = 0; kk < kRK; kk += 4) {
+        if (kk >= kval) break;
         const int r = kk + (lane >> 4);
         double2 a[2], b[2];
 #pragma unroll
@@ -273,6 +281,55 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
                   make_double2(accr[ta][tb][r], acci[ta][tb][r]);
       }
       __syncthreads();
+      if constexpr (kVec) {
+        // lanes 0-31 and 32-63 take two different columns; each lane two
+        // consecutive rows (one 16-byte access of X and of W)
+        const int rp = 2 * (lane & 31), cs = lane >> 5;
+        const int64_t nv = n0 + rp;
+        f4v xv[4];
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+          const int64_t j = j0 + 32 * h + 8 * wave + 2 * c2 + cs;
+          xv[c2] = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
+          if (j < M) {
+            const float* px = reinterpret_cast<const float*>(X + nv + j * ldX);
+            if (nv + 1 < N) {
+              xv[c2] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(px));
+            } else if (nv < N) {
+              xv[c2].x = px[0];
+              xv[c2].y = px[1];
+            }
+          }
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+          const int cl = 8 * wave + 2 * c2 + cs;
+          const int64_t j = j0 + 32 * h + cl;
+          if (j < M && nv < N) {
+            const double2 d0 = sD[cl][rp], d1 = sD[cl][rp + 1];
+            double w0r = (double)xv[c2].x - d0.x, w0i = (double)xv[c2].y - d0.y;
+            double w1r = (double)xv[c2].z - d1.x, w1i = (double)xv[c2].w - d1.y;
+            const bool two = nv + 1 < N;
+            if (W) {
+              const f4v wv = (f4v){(float)w0r, (float)w0i, (float)w1r, (float)w1i};
+              float* pw = reinterpret_cast<float*>(W + nv + j * ldW);
+              if (two) {
+                *reinterpret_cast<f4v*>(pw) = wv;
+              } else {
+                pw[0] = wv.x;
+                pw[1] = wv.y;
+              }
+              w0r = wv.x;
+              w0i = wv.y;
+              w1r = wv.z;
+              w1i = wv.w;
+            }
+            nacc[4 * h + c2] += w0r * w0r + w0i * w0i + (two ? w1r * w1r + w1i * w1i : 0.0);
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       double2 x[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -292,6 +349,24 @@ __global__ __launch_bounds__(256) void k_resid(const XT* X, int64_t ldX, WT* W, 
       }
       __syncthreads();
     }
+  }
+  if constexpr (kVec) {
+    // nacc[4 h + c2] holds rows of column 8 wave + 2 c2 + (lane >> 5) of
+    // half h: sum within each 32-lane half
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c2 = 0; c2 < 4; ++c2) {
+        double t = nacc[4 * h + c2];
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const int64_t j = j0 + 32 * h + 8 * wave + 2 * c2 + (lane >> 5);
+        if ((lane & 31) == 0 && j < M) {
+          nrm[j] = t;
+          if (!__builtin_isfinite(t)) *bad = 1;
+        }
+      }
+    return;
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -336,7 +411,17 @@ hipError_t launch_resid_t(const XT* X, int64_t ldX, WT* W, int64_t ldW, int64_t 
                           hipStream_t s) {
   if (M <= 0) return hipSuccess;
   dim3 grid((unsigned)((M + kRT - 1) / kRT));
-  hipLaunchKernelGGL((k_resid<XT, WT>), grid, dim3(256), 0, s, X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ, nrm, bad);
+  bool vec = false;
+  if constexpr (sizeof(XT) == 8 && sizeof(WT) == 8) {
+    vec = (ldX % 2 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+          (!W || ((ldW % 2 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0)));
+  }
+  if (vec)
+    hipLaunchKernelGGL((k_resid<XT, WT, true>), grid, dim3(256), 0, s, X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ,
+                       nrm, bad);
+  else
+    hipLaunchKernelGGL((k_resid<XT, WT, false>), grid, dim3(256), 0, s, X, ldX, W, ldW, N, M, E, ldE, m, C, cI, cJ,
+                       nrm, bad);
   return hipGetLastError();
 }
 
