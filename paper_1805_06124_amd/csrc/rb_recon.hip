@@ -127,6 +127,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double2* __restrict__
 // (round-robin pairing), columns then rows.  info: sweeps used, or -1 if
 // max_sweeps passed without a rotation-free sweep.
 constexpr int kJT = 1024;
+constexpr int kJU = 2;           // elements per thread per pass (loads first)
 constexpr int kMaxPairs = 1024;  // j <= 2048
 
 __global__ __launch_bounds__(kJT) void k_jacobi(double2* __restrict__ G, int64_t n, double2* __restrict__ V,
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi(double2* __restrict__ G, int64_t
   }
   const int64_t npr = n + (n & 1);
   const int64_t half = npr / 2;
+  const uint32_t nu = (uint32_t)n;  // n <= 2048: pair-element indices fit 32 bits
   int sweep = 0;
   bool done = false;
   for (; sweep < max_sweeps && !done; ++sweep) {
@@ -188,49 +190,91 @@ __global__ __launch_bounds__(kJT) void k_jacobi(double2* __restrict__ G, int64_t
       }
       __syncthreads();
       // ---- columns p, q of G and V: [x_p, x_q] <- [x_p, x_q] J ----
-      for (int64_t e = t; e < half * n; e += kJT) {
-        const int64_t i = e / n, row = e % n;
-        if (!sact[i]) continue;
-        const int64_t p = sp[i], q = sq[i];
-        const double c = sc[i], s = ss[i];
-        const double2 ph = sph[i];  // J = [[c, s], [-s conj(ph), c conj(ph)]]
-        {
-          const double2 xp = G[row + p * n], xq = G[row + q * n];
-          // xq * conj(ph)
-          const double2 y = make_double2(xq.x * ph.x + xq.y * ph.y, xq.y * ph.x - xq.x * ph.y);
-          G[row + p * n] = make_double2(c * xp.x - s * y.x, c * xp.y - s * y.y);
-          G[row + q * n] = make_double2(s * xp.x + c * y.x, s * xp.y + c * y.y);
+      // each thread takes kJU elements at a time, all loads issued first
+      const int64_t total = half * n;
+      for (int64_t base = t; base < total; base += (int64_t)kJT * kJU) {
+        double2 gp[kJU], gq[kJU], vp[kJU], vq[kJU];
+        bool ok[kJU];
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+          const int64_t e = base + (int64_t)u * kJT;
+          ok[u] = false;
+          if (e < total) {
+            const int64_t i = (uint32_t)e / nu, row = (uint32_t)e % nu;
+            if (sact[i]) {
+              ok[u] = true;
+              const int64_t p = sp[i], q = sq[i];
+              gp[u] = G[row + p * n];
+              gq[u] = G[row + q * n];
+              vp[u] = V[row + p * n];
+              vq[u] = V[row + q * n];
+            }
+          }
         }
-        {
-          const double2 xp = V[row + p * n], xq = V[row + q * n];
-          const double2 y = make_double2(xq.x * ph.x + xq.y * ph.y, xq.y * ph.x - xq.x * ph.y);
-          V[row + p * n] = make_double2(c * xp.x - s * y.x, c * xp.y - s * y.y);
-          V[row + q * n] = make_double2(s * xp.x + c * y.x, s * xp.y + c * y.y);
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+          if (!ok[u]) continue;
+          const int64_t e = base + (int64_t)u * kJT;
+          const int64_t i = (uint32_t)e / nu, row = (uint32_t)e % nu;
+          const int64_t p = sp[i], q = sq[i];
+          const double c = sc[i], s = ss[i];
+          const double2 ph = sph[i];  // J = [[c, s], [-s conj(ph), c conj(ph)]]
+          // xq * conj(ph)
+          const double2 y = make_double2(gq[u].x * ph.x + gq[u].y * ph.y, gq[u].y * ph.x - gq[u].x * ph.y);
+          G[row + p * n] = make_double2(c * gp[u].x - s * y.x, c * gp[u].y - s * y.y);
+          G[row + q * n] = make_double2(s * gp[u].x + c * y.x, s * gp[u].y + c * y.y);
+          const double2 z = make_double2(vq[u].x * ph.x + vq[u].y * ph.y, vq[u].y * ph.x - vq[u].x * ph.y);
+          V[row + p * n] = make_double2(c * vp[u].x - s * z.x, c * vp[u].y - s * z.y);
+          V[row + q * n] = make_double2(s * vp[u].x + c * z.x, s * vp[u].y + c * z.y);
         }
       }
       __syncthreads();
       // ---- rows p, q of G: [y_p; y_q] <- J^H [y_p; y_q] ----
-      for (int64_t e = t; e < half * n; e += kJT) {
-        const int64_t i = e / n, col = e % n;
-        if (!sact[i]) continue;
-        const int64_t p = sp[i], q = sq[i];
-        if (col == p) {
-          G[p + p * n] = make_double2(sa[i], 0.0);
-          G[q + p * n] = make_double2(0.0, 0.0);
-          continue;
+      // element e = (column, pair) with the pair varying fastest, so the
+      // threads of a wave touch the rows of one column (a few cache lines)
+      const uint32_t hu = (uint32_t)half;
+      for (int64_t base = t; base < total; base += (int64_t)kJT * kJU) {
+        double2 yp[kJU], yq[kJU];
+        bool ok[kJU];
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+          const int64_t e = base + (int64_t)u * kJT;
+          ok[u] = false;
+          if (e < total) {
+            const int64_t i = (uint32_t)e % hu, col = (uint32_t)e / hu;
+            if (sact[i]) {
+              ok[u] = true;
+              const int64_t p = sp[i], q = sq[i];
+              if (col != p && col != q) {
+                yp[u] = G[p + col * n];
+                yq[u] = G[q + col * n];
+              }
+            }
+          }
         }
-        if (col == q) {
-          G[q + q * n] = make_double2(sd[i], 0.0);
-          G[p + q * n] = make_double2(0.0, 0.0);
-          continue;
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+          if (!ok[u]) continue;
+          const int64_t e = base + (int64_t)u * kJT;
+          const int64_t i = (uint32_t)e % hu, col = (uint32_t)e / hu;
+          const int64_t p = sp[i], q = sq[i];
+          if (col == p) {
+            G[p + p * n] = make_double2(sa[i], 0.0);
+            G[q + p * n] = make_double2(0.0, 0.0);
+            continue;
+          }
+          if (col == q) {
+            G[q + q * n] = make_double2(sd[i], 0.0);
+            G[p + q * n] = make_double2(0.0, 0.0);
+            continue;
+          }
+          const double c = sc[i], s = ss[i];
+          const double2 ph = sph[i];
+          // yq * ph
+          const double2 z = make_double2(yq[u].x * ph.x - yq[u].y * ph.y, yq[u].x * ph.y + yq[u].y * ph.x);
+          G[p + col * n] = make_double2(c * yp[u].x - s * z.x, c * yp[u].y - s * z.y);
+          G[q + col * n] = make_double2(s * yp[u].x + c * z.x, s * yp[u].y + c * z.y);
         }
-        const double c = sc[i], s = ss[i];
-        const double2 ph = sph[i];
-        const double2 yp = G[p + col * n], yq = G[q + col * n];
-        // yq * ph
-        const double2 z = make_double2(yq.x * ph.x - yq.y * ph.y, yq.x * ph.y + yq.y * ph.x);
-        G[p + col * n] = make_double2(c * yp.x - s * z.x, c * yp.y - s * z.y);
-        G[q + col * n] = make_double2(s * yp.x + c * z.x, s * yp.y + c * z.y);
       }
       __syncthreads();
     }
