@@ -180,6 +180,28 @@ def orthogonality(E):
     return float(torch.linalg.matrix_norm(G - torch.eye(k, dtype=G.dtype, device=G.device), ord=2))
 
 
+def achievable_read(rb, t, reps=3):
+    """Rate of a plain streaming read of the whole tensor t (rb_stream_read),
+    best of `reps`, in GB/s, timed with events on the stream it runs on."""
+    import torch
+    # 2,048 workgroups of 256 (8 per compute unit): the grid size at which a
+    # grid-stride read ran fastest on this chip (more workgroups read slower)
+    part = torch.empty(2048, dtype=torch.float64, device=t.device)
+    rb.stream_read(t, part)
+    best = None
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        rb.stream_read(t, part)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    nbytes = t.numel() * t.element_size()
+    return nbytes / (best * 1e-3) / 1e9
+
+
 def validation_leg(rb, ri, w, E, tol, n_cols, log):
     """Out-of-sample validation of the final basis on n_cols held-out chirps
     (seed HELDOUT_SEED, generated on the device in chunks) and one enrichment
@@ -313,6 +335,8 @@ def main():
     if w.dtype == "c128":
         log("generating %s: N=%d M=%d (%.1f GB complex128)" % (w.name, w.N, w.M, 16 * w.N * w.M / 1e9))
         S = rb.chirp_fill(params, w.N, w.flo, w.fhi)
+        read_gbs = achievable_read(rb, S)
+        log("plain streaming read of S: %.1f GB/s" % read_gbs)
         Wk = torch.empty_like(S)
         runs = timed_runs(lambda: rb.greedy(S, tol, w.kmax, W=Wk), args.steps, args.warmup, log, "fp64")
         t_run = sum(dt for dt, _ in runs) / len(runs)
@@ -328,7 +352,9 @@ def main():
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "traffic": measured_traffic("k_sweep_z", w.name),
-                              "ms_per_launch": ms, "bytes_per_launch": by},
+                              "ms_per_launch": ms, "bytes_per_launch": by,
+                              "achievable_read_GBs": read_gbs,
+                              "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read_gbs},
                     breakdown_ms={"sweep": st["ms_sweep"], "gs": st["ms_gs"], "anchor": st["ms_anchor"],
                                   "total": st["ms_total"]})
         log("fp64 sweep: %.3f ms/launch, %.1f GB/s; gs %.1f ms, anchors %.1f ms (%d)" % (
@@ -372,6 +398,8 @@ def main():
     if w.dtype == "c64" or not args.no_mixed:
         log("generating complex64 storage: N=%d M=%d (%.1f GB)" % (w.N, w.M, 8 * w.N * w.M / 1e9))
         S32 = rb.chirp_fill(params, w.N, w.flo, w.fhi, dtype=torch.complex64)
+        read32 = achievable_read(rb, S32)
+        log("plain streaming read of S32: %.1f GB/s" % read32)
         W32 = torch.empty_like(S32)
         runs = timed_runs(lambda: rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32), args.steps,
                           args.warmup, log, "mixed")
@@ -389,7 +417,9 @@ def main():
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                "traffic": measured_traffic("k_sweep_c", w.name.replace("c128", "c64")),
-                               "ms_per_launch": ms, "bytes_per_launch": by},
+                               "ms_per_launch": ms, "bytes_per_launch": by,
+                               "achievable_read_GBs": read32,
+                               "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read32},
                      breakdown_ms={"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
                                    "total": st["ms_total"]})
         log("mixed sweep: %.3f ms/launch, %.1f GB/s; confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (

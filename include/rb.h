@@ -408,6 +408,33 @@ int rb_eim_errors_z(const void *R, int64_t N, int64_t k, int64_t ldR, const void
  *   params  device, double[2*M]: (Mtot in solar masses, q) per column (read)
  *   out     device, complex128 (dtype 0) or complex64 (dtype 1), N x M, ld
  */
+/*
+ * rb_chirp_params -- parameters of the chirp family from a seed: column
+ * start + t (t < M) takes Mtot = mlo + (mhi - mlo) u(seed, 2 (start + t)) and
+ * q = qlo + (qhi - qlo) u(seed, 2 (start + t) + 1), where u(seed, i) =
+ * (z >> 11) 2^-53 and z is the SplitMix64 output for counter i (Steele, Lea
+ * & Flood 2014: state seed + (i + 1) 0x9E3779B97F4A7C15, finaliser
+ * xor-shift 30, times 0xBF58476D1CE4E5B9, xor-shift 27, times
+ * 0x94D049BB133111EB, xor-shift 31).  Every operation is rounded on its
+ * own (no fused multiply-add).
+ *   params  device, double[2*M]: (Mtot in solar masses, q) per column (out)
+ * Enqueued on stream (not synchronised).
+ */
+int rb_chirp_params(uint64_t seed, int64_t start, int64_t M, double mlo, double mhi, double qlo, double qhi,
+                    double *params, hipStream_t stream);
+
+/*
+ * rb_stream_read -- reads `bytes` of device memory once with 16-byte
+ * streaming loads and writes one partial sum per workgroup to
+ * partial[0..npartial) (device).  This is a plain read whose rate is the
+ * achievable HBM bandwidth, measured beside the sweep.  npartial is the
+ * grid size (workgroups of 256 threads in a grid-stride loop; 2048, eight
+ * per compute unit, reads fastest on MI355X).  bytes is a multiple of 16,
+ * p is 16-byte aligned, and 1 <= npartial <= 65535.
+ * Enqueued on stream (not synchronised).
+ */
+int rb_stream_read(const void *p, size_t bytes, double *partial, int64_t npartial, hipStream_t stream);
+
 int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64_t N, int dtype, void *out,
                   int64_t ld, hipStream_t stream);
 

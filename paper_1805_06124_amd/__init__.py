@@ -54,7 +54,8 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
-           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z"]
+           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z",
+           "rb_chirp_params", "rb_stream_read"]
 
 _lib = None
 
@@ -96,6 +97,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_eim_z.argtypes = [P, I64, I64, I64, P, P, P, P, ctypes.POINTER(I64), P]
     L.rb_eim_errors_z.restype = ctypes.c_int
     L.rb_eim_errors_z.argtypes = [P, I64, I64, I64, P, P, P, I64, I64, P, P]
+    L.rb_chirp_params.restype = ctypes.c_int
+    L.rb_chirp_params.argtypes = [ctypes.c_uint64, I64, I64, D, D, D, D, P, P]
+    L.rb_stream_read.restype = ctypes.c_int
+    L.rb_stream_read.argtypes = [P, ctypes.c_size_t, P, I64, P]
     L.rb_sweep_c.restype = ctypes.c_int
     L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
     L.rb_greedy_c.restype = ctypes.c_int
@@ -447,6 +452,27 @@ def eim_errors(ei: dict, V: torch.Tensor, stream=None) -> torch.Tensor:
     _check("rb_eim_errors_z", load().rb_eim_errors_z(_ptr(R), N, k, ldR, _ptr(Tcm), _ptr(nodes), _ptr(V), M, ldV,
                                                      _ptr(out), _stream(stream)))
     return out
+
+
+def chirp_params(seed: int, M: int, mlo: float, mhi: float, qlo: float, qhi: float, start: int = 0,
+                 device="cuda", stream=None) -> torch.Tensor:
+    """(M, 2) float64 GPU tensor of chirp parameters (Mtot, q) for columns
+    start .. start + M - 1 from the seed (SplitMix64 counters)."""
+    out = torch.empty((M, 2), dtype=torch.float64, device=device)
+    _check("rb_chirp_params", load().rb_chirp_params(int(seed) & (2 ** 64 - 1), int(start), int(M), float(mlo),
+                                                     float(mhi), float(qlo), float(qhi), _ptr(out),
+                                                     _stream(stream)))
+    return out
+
+
+def stream_read(t: torch.Tensor, partial: torch.Tensor, stream=None) -> None:
+    """Read the whole of tensor t once (plain streaming read, partial sums
+    into the float64 tensor `partial`, one per workgroup)."""
+    if not t.is_cuda or not t.is_contiguous() or partial.dtype != torch.float64 or not partial.is_cuda:
+        raise ValueError("stream_read needs a contiguous GPU tensor and a float64 GPU partial buffer")
+    nbytes = t.numel() * t.element_size()
+    _check("rb_stream_read", load().rb_stream_read(_ptr(t), nbytes - nbytes % 16, _ptr(partial), partial.numel(),
+                                                   _stream(stream)))
 
 
 def chirp_fill(params: torch.Tensor, N: int, flo: float, fhi: float, dtype=torch.complex128,

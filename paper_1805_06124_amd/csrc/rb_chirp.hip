@@ -15,7 +15,9 @@
 //   A = 3/(128 eta) (pi Mtot)^(-5/3),  B = 3/(128 eta) (3715/756 + 55 eta/9) / (pi Mtot).
 // A row table (f_n^(-7/6)/||h||, f_n^(-5/3), 1/f_n) is built once; each
 // element then costs two FMAs, one sincos and two products, in one pass.
-#include "rb_internal.h"
+#include <cmath>
+
+#include "rb_host.h"
 
 namespace rb {
 
@@ -99,3 +101,85 @@ hipError_t launch_chirp_fill(const double* params, const int64_t* cols, int64_t 
 }
 
 }  // namespace rb
+
+// ---------------------------------------------------------------------------
+// Parameters of the chirp family from a seed: SplitMix64 (Steele, Lea &
+// Flood 2014) counter outputs mapped to uniform doubles (z >> 11) 2^-53;
+// column j takes Mtot from counter 2 j and q from counter 2 j + 1.  The
+// affine maps are rounded step by step (contraction into fused
+// multiply-adds is switched off), so the values are the same bits as any
+// other implementation of these formulas.
+namespace rb {
+namespace {
+
+__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1p-53;
+}
+
+__global__ __launch_bounds__(256) void k_chirp_params(uint64_t seed, int64_t start, int64_t M, double mlo, double mhi,
+                                                      double qlo, double qhi, double* __restrict__ params) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= M) return;
+  {
+#pragma clang fp contract(off)
+    const uint64_t j = (uint64_t)(start + t);
+    const double um = splitmix_uniform(seed, 2ull * j), uq = splitmix_uniform(seed, 2ull * j + 1ull);
+    const double dm = mhi - mlo, dq = qhi - qlo;
+    const double pm = dm * um, pq = dq * uq;
+    params[2 * t] = mlo + pm;
+    params[2 * t + 1] = qlo + pq;
+  }
+}
+
+// sum of every double of a buffer read once with 16-byte streaming loads
+// (the plain read whose rate is the achievable HBM bandwidth); one partial
+// sum per block
+__global__ __launch_bounds__(256) void k_stream_read(const double2* __restrict__ p, int64_t n2,
+                                                     double* __restrict__ partial) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) {
+    const double2 a = ld_stream(p + i);
+    s0 += a.x;
+    s1 += a.y;
+  }
+  const double s = wave_sum(s0 + s1);
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+}  // namespace
+}  // namespace rb
+
+extern "C" {
+
+int rb_chirp_params(uint64_t seed, int64_t start, int64_t M, double mlo, double mhi, double qlo, double qhi,
+                    double* params, hipStream_t stream) {
+  rb::last_error().clear();
+  if (!params || M <= 0 || start < 0 || !(mhi >= mlo) || !(qhi >= qlo) || !std::isfinite(mlo) ||
+      !std::isfinite(mhi) || !std::isfinite(qlo) || !std::isfinite(qhi))
+    return rb::set_error(RB_EINVAL, "rb_chirp_params: bad arguments");
+  hipLaunchKernelGGL(rb::k_chirp_params, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream, seed, start, M, mlo,
+                     mhi, qlo, qhi, params);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_stream_read(const void* p, size_t bytes, double* partial, int64_t npartial, hipStream_t stream) {
+  rb::last_error().clear();
+  if (!p || !partial || bytes < 16 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(p) % 16) != 0 ||
+      npartial < 1 || npartial > 65535)
+    return rb::set_error(RB_EINVAL, "rb_stream_read: bad arguments");
+  hipLaunchKernelGGL(rb::k_stream_read, dim3((unsigned)npartial), dim3(256), 0, stream,
+                     static_cast<const double2*>(p), (int64_t)(bytes / 16), partial);
+  RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+}  // extern "C"

@@ -258,3 +258,26 @@ def test_project_matches_oracle(rb, N, k, M):
     ref = oracle.project(E_host, S_host)                      # (k, M)
     scale = np.linalg.norm(E_host, axis=1)[None, :] * np.linalg.norm(S_host, axis=1)[:, None]
     assert np.all(np.abs(C - ref.T) <= 16 * U * np.sqrt(N) * scale)
+
+
+def test_chirp_params_bit_exact(rb):
+    """The device parameter generator (SplitMix64 counters, step-by-step
+    rounded affine maps) returns the same bits as the shared seeded
+    generator, including a large counter offset."""
+    cases = [(1805, 409600, 0, (20.0, 60.0, 1.0, 4.0)), (1806, 1000, 12345, (40.0, 60.0, 1.0, 4.0)),
+             (7, 3, 2 ** 33, (20.0, 80.0, 1.0, 8.0))]
+    for seed, M, start, rng in cases:
+        got = rb.chirp_params(seed, M, *rng, start=start).cpu().numpy()
+        want = ri.chirp_params(seed, M, *rng, start=start)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_stream_read_sums(rb):
+    """The plain streaming read visits every element once: its partial sums
+    add up to the sum of the buffer (exactly representable values)."""
+    x = torch.arange(1, 2 * 1000003 + 1, dtype=torch.float64, device="cuda").view(-1, 2)
+    x = torch.view_as_complex(x.contiguous())
+    part = torch.zeros(64, dtype=torch.float64, device="cuda")
+    rb.stream_read(x, part)
+    n = 2 * 1000003
+    assert part.sum().item() == n * (n + 1) / 2
