@@ -180,6 +180,33 @@ def orthogonality(E):
     return float(torch.linalg.matrix_norm(G - torch.eye(k, dtype=G.dtype, device=G.device), ord=2))
 
 
+def agreement(piv_ref, err_ref, piv, err):
+    """Agreement of a run with a reference run on the same inputs.
+
+    Returns:
+    - the share of steps with the same pivot;
+    - the first step where the pivots differ (None if never);
+    - the share of pivots the two runs have in common as sets;
+    - the largest and the median relative deviation of the error sequence
+      over the common steps.
+    A near-tie decided differently (unit-norm columns tie at step 0) shifts
+    every later pivot without changing the greedy's quality; the common set
+    and the error sequence show that."""
+    import numpy as np
+    n = min(len(piv_ref), len(piv))
+    same = np.asarray(piv_ref[:n]) == np.asarray(piv[:n])
+    first = None if same.all() else int(np.argmin(same))
+    common = len(set(np.asarray(piv_ref).tolist()) & set(np.asarray(piv).tolist()))
+    m = min(len(err_ref), len(err))
+    e0, e1 = np.asarray(err_ref[:m]), np.asarray(err[:m])
+    rel = np.abs(e1 - e0) / np.maximum(e0, 1e-300)
+    return {"pivot_agreement": float(same.mean()) if n else 1.0, "first_divergence": first,
+            "common_pivots": common / max(len(piv_ref), 1),
+            "err_rel_deviation_max": float(rel.max()) if m else 0.0,
+            "err_rel_deviation_median": float(np.median(rel)) if m else 0.0,
+            "k_ref": len(piv_ref), "k": len(piv)}
+
+
 def achievable_read(rb, t, reps=3):
     """Rate of a plain streaming read of the whole tensor t (rb_stream_read),
     best of `reps`, in GB/s, timed with events on the stream it runs on."""
@@ -329,6 +356,7 @@ def main():
         "vs_baseline": None, "data": "synthetic",
     }
     fp64 = None
+    fp64_trace = None
     proj = None
     sur_out = None
     val_out = None
@@ -345,6 +373,7 @@ def main():
         st = gs["stats"]
         ms = st["ms_sweep"] / max(st["sweeps"], 1)
         by = sweep_bytes(w.N, w.M)
+        fp64_trace = (g["piv"].copy(), g["err"].copy())
         fp64 = dict(value=sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), time_to_tol_s=t_run,
                     k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                     anchors=int(g["stats"]["anchors"]), orthogonality=orthogonality(g["E"]),
@@ -413,6 +442,8 @@ def main():
                      k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                      anchors=int(g["stats"]["anchors"]), exact_anchors=int(g["stats"]["regen_anchors"]),
                      misses=int(g["stats"]["misses"]), orthogonality=orthogonality(g["E"]),
+                     vs_fp64=(agreement(fp64_trace[0], fp64_trace[1], g["piv"], g["err"])
+                              if fp64_trace is not None else None),
                      roofline={"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -424,6 +455,12 @@ def main():
                                    "total": st["ms_total"]})
         log("mixed sweep: %.3f ms/launch, %.1f GB/s; confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (
             ms, mixed["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
+        if mixed["vs_fp64"] is not None:
+            a = mixed["vs_fp64"]
+            log("mixed vs fp64: pivot agreement %.3f (first divergence at step %s), common pivots %.3f, "
+                "relative error deviation median %.3g max %.3g, k %d vs %d" % (
+                    a["pivot_agreement"], a["first_divergence"], a["common_pivots"], a["err_rel_deviation_median"],
+                    a["err_rel_deviation_max"], a["k"], a["k_ref"]))
         del S32, W32, g, gs, runs
         torch.cuda.empty_cache()
 
