@@ -13,15 +13,21 @@
  *    with ld = N.
  *  - Pointers documented as "device" must point to device memory of the
  *    current HIP device; "host" pointers to ordinary host memory.  All memory
- *    passed in is owned by the caller; the library never frees it.  The
- *    library allocates its own scratch (O(M) words plus, for the greedy, an
- *    m x M coefficient panel) with hipMalloc and frees it before returning.
- *  - Work is enqueued on the given stream (NULL = the default stream); every
- *    call returns after that work has completed, because the greedy takes a
- *    host decision after every step.
+ *    passed in is owned by the caller; the library never frees it.  Each
+ *    call allocates the scratch it needs with hipMalloc and frees it before
+ *    returning (the large ones are stated with each entry point: the
+ *    greedy's anchor_max x M coefficient panel, regeneration chunks,
+ *    coefficient workspaces).
+ *  - Work is enqueued on the given stream (NULL = the default stream).
+ *    Calls return after that work has completed (the greedy takes a host
+ *    decision after every step), except those documented as "enqueued, not
+ *    synchronised": rb_chirp_table, rb_chirp_regen, rb_chirp_params and
+ *    rb_stream_read.
  *  - Return value: an rb_status code.  Arguments are validated on the host
- *    before any device work; on error nothing is written.  rb_last_error()
- *    gives a message for the last failing call on the calling thread.
+ *    before any device work; a call that fails later (a device error, a
+ *    non-finite value found on the way) may have written part of its
+ *    outputs.  rb_last_error() gives a message for the last failing call on
+ *    the calling thread.
  *  - Inner product: <e, s> = e^H s (the paper's real transpose read as the
  *    conjugate transpose); norms are Euclidean, unweighted.
  */
@@ -45,7 +51,8 @@ typedef enum rb_status {
   RB_EINVAL = -1,       /* bad dimensions, pointers or options */
   RB_ENOMEM = -2,       /* device allocation failed */
   RB_EDEVICE = -3,      /* HIP runtime error or no usable device */
-  RB_ENONFINITE = -4,   /* S holds a NaN or Inf (or a column norm overflows) */
+  RB_ENONFINITE = -4,   /* an input (S, V) holds a NaN or Inf, or a norm
+                           overflows */
   RB_ENOCONV = -5       /* an iterative eigen-solve did not converge */
 } rb_status;
 
@@ -211,10 +218,11 @@ typedef struct rb_chirp_ctx {
  * share it): table[3n] = f_n^(-7/6) / ||h||, table[3n+1] = f_n^(-5/3),
  * table[3n+2] = 1/f_n, where ||h||^2 = sum_n f_n^(-7/3) is every column's
  * squared norm (the amplitude does not depend on the phase).  Enqueued on
- * stream (not synchronised). */
+ * stream; enqueued, not synchronised. */
 int rb_chirp_table(double flo, double fhi, int64_t N, double *table, hipStream_t stream);
 
-/* rb_regen_fn for the chirp family (ctx is a rb_chirp_ctx*). */
+/* rb_regen_fn for the chirp family (ctx is a rb_chirp_ctx*); enqueued, not
+ * synchronised. */
 int rb_chirp_regen(void *ctx, const int64_t *cols, int64_t n, void *out, int64_t ldo, hipStream_t stream);
 
 /*
@@ -418,7 +426,7 @@ int rb_eim_errors_z(const void *R, int64_t N, int64_t k, int64_t ldR, const void
  * 0x94D049BB133111EB, xor-shift 31).  Every operation is rounded on its
  * own (no fused multiply-add).
  *   params  device, double[2*M]: (Mtot in solar masses, q) per column (out)
- * Enqueued on stream (not synchronised).
+ * Enqueued, not synchronised.
  */
 int rb_chirp_params(uint64_t seed, int64_t start, int64_t M, double mlo, double mhi, double qlo, double qhi,
                     double *params, hipStream_t stream);
@@ -431,7 +439,7 @@ int rb_chirp_params(uint64_t seed, int64_t start, int64_t M, double mlo, double 
  * grid size (workgroups of 256 threads in a grid-stride loop; 2048, eight
  * per compute unit, reads fastest on MI355X).  bytes is a multiple of 16,
  * p is 16-byte aligned, and 1 <= npartial <= 65535.
- * Enqueued on stream (not synchronised).
+ * Enqueued, not synchronised.
  */
 int rb_stream_read(const void *p, size_t bytes, double *partial, int64_t npartial, hipStream_t stream);
 
