@@ -218,7 +218,7 @@ typedef struct rb_chirp_ctx {
  * share it): table[3n] = f_n^(-7/6) / ||h||, table[3n+1] = f_n^(-5/3),
  * table[3n+2] = 1/f_n, where ||h||^2 = sum_n f_n^(-7/3) is every column's
  * squared norm (the amplitude does not depend on the phase).  Enqueued on
- * stream; enqueued, not synchronised. */
+ * stream, not synchronised. */
 int rb_chirp_table(double flo, double fhi, int64_t N, double *table, hipStream_t stream);
 
 /* rb_regen_fn for the chirp family (ctx is a rb_chirp_ctx*); enqueued, not
