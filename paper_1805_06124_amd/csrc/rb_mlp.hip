@@ -42,8 +42,9 @@ constexpr int kGT = 64, kGK = 32, kGKP = kGK + 8;
 
 // Stage the 64 x 32 tile X(r0 + r, k0 + kk) = X[r*sr + k*sk] (r < 64,
 // kk < 32) into LDS as dst[r][kk].  vec: 1 = K contiguous (sk == 1), 2 = R
-// contiguous (sr == 1), with 16-byte aligned rows, else 0 (scalar loads).
-// Each thread moves 8 values.
+// contiguous (sr == 1), with 16-byte aligned rows (one 16-byte load per
+// thread); 3 and 4 the same with 4-byte aligned rows (four 4-byte loads);
+// else 0 (scalar loads).  Each thread moves 8 values.
 __device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64_t sr, int64_t sk, int64_t R,
                                            int64_t K, int64_t r0, int64_t k0, int vec, uint16_t (*dst)[kGKP],
                                            int tid) {
@@ -72,6 +73,38 @@ __device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) dst[r + i][kk] = t[i];
+  } else if (vec == 3) {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    const int64_t gr = r0 + r, gk = k0 + kk;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (gr < R && gk + 7 < K) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gr * sr + gk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = src[i];
+    } else if (gr < R) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = (gk + 2 * i < K) ? X[gr * sr + gk + 2 * i] : 0u;
+        const uint32_t hi = (gk + 2 * i + 1 < K) ? X[gr * sr + gk + 2 * i + 1] : 0u;
+        w[i] = lo | (hi << 16);
+      }
+    }
+    *reinterpret_cast<uint4*>(&dst[r][kk]) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if (vec == 4) {
+    const int kk = tid >> 3, r = (tid & 7) * 8;
+    const int64_t gr = r0 + r, gk = k0 + kk;
+    if (gk < K && gr + 7 < R) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gk * sk + gr);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t w = src[i];
+        dst[r + 2 * i][kk] = (uint16_t)(w & 0xffffu);
+        dst[r + 2 * i + 1][kk] = (uint16_t)(w >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[r + i][kk] = (gk < K && gr + i < R) ? X[gk * sk + gr + i] : (uint16_t)0;
+    }
   } else {
     const int r = tid >> 2, kk = (tid & 3) * 8;
     const int64_t gr = r0 + r;
@@ -83,13 +116,15 @@ __device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64
   }
 }
 
+// Split over K (kEpiStore only): workgroup z reduces k in [z kc, (z+1) kc)
+// and stores its partial product at C + z cz; one split is kc = K, cz = 0.
 template <int kEpi>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
                                                    int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
                                                    int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ Cb,
                                                    int64_t ldcb, const uint16_t* __restrict__ H, int64_t ldh,
-                                                   int vecA, int vecB) {
+                                                   int vecA, int vecB, int64_t kc, int64_t cz) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
   __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -101,9 +136,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t k0 = 0; k0 < K; k0 += kGK) {
-    stage_tile(A, sam, sak, M, K, m0, k0, vecA, sA, tid);
-    stage_tile(B, sbn, sbk, N, K, n0, k0, vecB, sB, tid);
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = (kb + kc < K) ? kb + kc : K;
+  if (kEpi == kEpiStore) C += (int64_t)blockIdx.z * cz;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
+    stage_tile(A, sam, sak, M, ke, m0, k0, vecA, sA, tid);
+    stage_tile(B, sbn, sbk, N, ke, n0, k0, vecB, sB, tid);
     __syncthreads();
     bf16x8 a[2], b[2];
 #pragma unroll
@@ -158,7 +196,7 @@ __global__ __launch_bounds__(256) void k_layer1_fwd(const float* __restrict__ X,
 // and, if X is given, dW[i][o] = sum_b X[b][i] D[b][o] (i < din).  Partial
 // sums per workgroup row chunk go to part[(chunk)(din+1) d], reduced by
 // k_colsum_final in a fixed order.
-constexpr int kColRows = 256;
+constexpr int kColRows = 32;
 __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ D, int64_t B, int d,
                                                 const float* __restrict__ X, int din, float* __restrict__ part) {
   const int o = blockIdx.x * 256 + threadIdx.x;
@@ -176,16 +214,36 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ D, 
   p[o] = s;
   for (int i = 0; i < nx; ++i) p[(int64_t)(i + 1) * d + o] = sx[i];
 }
+// the partial sums of k_colsum added per output: 64 outputs per workgroup,
+// four threads per output each adding every fourth chunk, the four sums
+// then added in a fixed order
 __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int64_t chunks, int64_t len,
                                                       float* __restrict__ db, float* __restrict__ dW, int d) {
+  __shared__ float sred[4][64];
+  const int ol = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + ol;
+  float s = 0.f;
+  if (t < len)
+    for (int64_t c = q; c < chunks; c += 4) s += part[c * len + t];
+  sred[q][ol] = s;
+  __syncthreads();
+  if (q == 0 && t < len) {
+    const float v = (sred[0][ol] + sred[1][ol]) + (sred[2][ol] + sred[3][ol]);
+    if (t < d)
+      db[t] = v;
+    else
+      dW[t - d] = v;
+  }
+}
+
+// C[t] = sum over z of P[z len + t], in order of z
+__global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ P, int splits, int64_t len,
+                                                       float* __restrict__ C) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= len) return;
   float s = 0.f;
-  for (int64_t c = 0; c < chunks; ++c) s += part[c * len + t];
-  if (t < d)
-    db[t] = s;
-  else
-    dW[t - d] = s;
+  for (int z = 0; z < splits; ++z) s += P[(int64_t)z * len + t];
+  C[t] = s;
 }
 
 // MSE loss and its gradient: dY = bf16(2 (Y - T) / (B d)); per-block
@@ -286,6 +344,9 @@ int vec_mode(const uint16_t* X, int64_t sr, int64_t sk) {
   const bool al = (reinterpret_cast<uintptr_t>(X) & 15) == 0;
   if (al && sk == 1 && (sr * 2) % 16 == 0) return 1;
   if (al && sr == 1 && (sk * 2) % 16 == 0) return 2;
+  const bool al4 = (reinterpret_cast<uintptr_t>(X) & 3) == 0;
+  if (al4 && sk == 1 && sr % 2 == 0) return 3;
+  if (al4 && sr == 1 && sk % 2 == 0) return 4;
   return 0;
 }
 
@@ -297,7 +358,31 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam,
   if (grid.y > 65535) return hipErrorInvalidValue;
   const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
   hipLaunchKernelGGL(k_gemm_bf16<kEpi>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Cb,
-                     ldcb, H, ldh, vecA, vecB);
+                     ldcb, H, ldh, vecA, vecB, K, (int64_t)0);
+  return hipGetLastError();
+}
+
+// Weight gradients C (M x N, ldc = N) = A B with a long reduction K (the
+// batch): kSplitK workgroups per output tile each reduce a K range of at
+// least kSplitMin into P (kSplitK x M x N floats), then the splits are added
+// in a fixed order.
+constexpr int kSplitK = 16;
+constexpr int64_t kSplitMin = 128;
+hipError_t gemm_splitk(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam, int64_t sak,
+                       const uint16_t* B, int64_t sbk, int64_t sbn, float* C, float* P, hipStream_t s) {
+  int splits = kSplitK;
+  while (splits > 1 && (K + splits - 1) / splits < kSplitMin) splits /= 2;
+  int64_t kc = (K + splits - 1) / splits;
+  kc = (kc + kGK - 1) / kGK * kGK;  // whole staging chunks
+  splits = (int)((K + kc - 1) / kc);
+  dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT), (unsigned)splits);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
+  hipLaunchKernelGGL(k_gemm_bf16<kEpiStore>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, P, N,
+                     nullptr, nullptr, 0, nullptr, 0, vecA, vecB, kc, M * N);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, P, splits, M * N, C);
   return hipGetLastError();
 }
 
@@ -324,7 +409,7 @@ hipError_t colsum(const uint16_t* D, int64_t B, int d, const float* X, int din, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t len = (int64_t)((X ? din : 0) + 1) * d;
-  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part, chunks, len, db, dW,
+  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 63) / 64)), dim3(256), 0, s, part, chunks, len, db, dW,
                      d);
   return hipGetLastError();
 }
@@ -346,15 +431,16 @@ size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
   if (batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return 0;
   const int64_t chunks = (batch + kColRows - 1) / kColRows;
   const int64_t part = chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout);
-  // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums
+  const int64_t splitk = (int64_t)kSplitK * hidden * (hidden > dout ? hidden : dout);
+  // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums (column sums,
+  // then the split-K partials of the weight gradients)
   return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout) * 2 + (size_t)batch * dout * 4 +
-         (size_t)(part + 4096) * 4 + 1024;
+         (size_t)(part + 4096 + splitk) * 4 + 1024;
 }
 
 // Workspace carve-up (byte offsets) shared by forward and backward.
 static void carve(void* ws, int64_t batch, int din, int hidden, int dout, uint16_t** H, uint16_t** dz,
-                  uint16_t** dY, float** Y, float** part) {
-  (void)din;
+                  uint16_t** dY, float** Y, float** part, float** splitp = nullptr) {
   char* p = static_cast<char*>(ws);
   for (int l = 0; l < 3; ++l) {
     H[l] = reinterpret_cast<uint16_t*>(p);
@@ -370,6 +456,10 @@ static void carve(void* ws, int64_t batch, int din, int hidden, int dout, uint16
   *Y = reinterpret_cast<float*>(p);
   p += (size_t)batch * dout * 4;
   *part = reinterpret_cast<float*>(p);
+  if (splitp) {
+    const int64_t chunks = (batch + kColRows - 1) / kColRows;
+    *splitp = *part + chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout) + 4096;
+  }
 }
 
 int rb_mlp_forward(const float* p32, const uint16_t* p16, int din, int hidden, int dout, const float* X,
@@ -422,24 +512,21 @@ int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, 
     return set_error(RB_EINVAL, "rb_mlp_backward: bad arguments");
   const Layout L(din, hidden, dout);
   uint16_t *H[3], *dz[2], *dY;
-  float *Yw, *part;
-  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part);
+  float *Yw, *part, *splitp;
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp);
   if (dY_in) dY = const_cast<uint16_t*>(dY_in);
   // output layer: dW4 = H3^T dY, db4 = colsum(dY), dZ3 = (dY W4^T) * (1 - H3^2)
-  RB_HIP(gemm<kEpiStore>(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, grad + L.W4, dout, nullptr, nullptr, 0,
-                         nullptr, 0, stream));
+  RB_HIP(gemm_splitk(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, grad + L.W4, splitp, stream));
   RB_HIP(colsum(dY, batch, dout, nullptr, din, part, grad + L.b4, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, dout, dY, dout, 1, p16 + L.W4, 1, dout, nullptr, 0, nullptr, dz[0], hidden,
                          H[2], hidden, stream));
   // hidden layer 3: dW3 = H2^T dZ3, db3, dZ2 = (dZ3 W3^T) * (1 - H2^2)
-  RB_HIP(gemm<kEpiStore>(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, grad + L.W3, hidden, nullptr,
-                         nullptr, 0, nullptr, 0, stream));
+  RB_HIP(gemm_splitk(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, grad + L.W3, splitp, stream));
   RB_HIP(colsum(dz[0], batch, hidden, nullptr, din, part, grad + L.b3, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[0], hidden, 1, p16 + L.W3, 1, hidden, nullptr, 0, nullptr, dz[1],
                          hidden, H[1], hidden, stream));
   // hidden layer 2: dW2 = H1^T dZ2, db2, dZ1 = (dZ2 W2^T) * (1 - H1^2)
-  RB_HIP(gemm<kEpiStore>(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, grad + L.W2, hidden, nullptr,
-                         nullptr, 0, nullptr, 0, stream));
+  RB_HIP(gemm_splitk(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, grad + L.W2, splitp, stream));
   RB_HIP(colsum(dz[1], batch, hidden, nullptr, din, part, grad + L.b2, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[1], hidden, 1, p16 + L.W2, 1, hidden, nullptr, 0, nullptr, dz[0],
                          hidden, H[0], hidden, stream));

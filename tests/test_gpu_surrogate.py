@@ -41,8 +41,12 @@ def test_forward_matches_oracle(rb):
     assert np.max(np.abs(Y - Yr)) <= 4 * 2 ** -8 * np.max(np.abs(Yr))
 
 
-def test_gradients_match_oracle(rb):
-    sur, p, X, T, (din, h, dout) = _setup(rb)
+@pytest.mark.parametrize("k,B", [(47, 300), (141, 4096)])
+def test_gradients_match_oracle(rb, k, B):
+    """Also at the training shape (k = 141, batch 4,096): 16 splits of the
+    batch reduction for the weight gradients, 128 column-sum chunks, and
+    output rows 2k = 282 wide (4-byte aligned staging)."""
+    sur, p, X, T, (din, h, dout) = _setup(rb, k=k, B=B)
     Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
     Y = sur.forward(Xd)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
