@@ -19,7 +19,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------- project --
 // C = E^H S.  A workgroup owns a block of 32*kTA basis vectors (i) x 64
 // columns (j); 4 waves as 2 x 2, each wave 16*kTA x 32 = kTA x 2 MFMA 16x16
-// tiles.  With kTA = 5 a block covers k <= 160, so S is read once.  The
+// tiles.  With kTA up to 7 a block covers k <= 224, so S is read once.  The
 // reduction runs over rows n in chunks of 16 staged through LDS as
 // [n][col]; the next chunk is loaded into registers while the matrix cores
 // work on the current one.
@@ -395,12 +395,17 @@ hipError_t launch_project_t(const double2* E, int64_t N, int64_t k, int64_t ldE,
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s) {
   if (k <= 0 || M <= 0) return hipSuccess;
-  // smallest block height (32 kTA) that covers k in one block, up to 160
-  switch (k <= 32 ? 1 : k <= 64 ? 2 : k <= 96 ? 3 : k <= 128 ? 4 : 5) {
+  // fewest passes over S with blocks of at most 224 basis vectors, k split
+  // evenly between them; block height 32 kTA
+  const int64_t passes = (k + 223) / 224;
+  const int64_t per = (k + passes - 1) / passes;
+  switch ((int)((per + 31) / 32)) {
     case 1: return launch_project_t<1>(E, N, k, ldE, S, M, ldS, C, ldC, s);
     case 2: return launch_project_t<2>(E, N, k, ldE, S, M, ldS, C, ldC, s);
     case 3: return launch_project_t<3>(E, N, k, ldE, S, M, ldS, C, ldC, s);
     case 4: return launch_project_t<4>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    case 6: return launch_project_t<6>(E, N, k, ldE, S, M, ldS, C, ldC, s);
+    case 7: return launch_project_t<7>(E, N, k, ldE, S, M, ldS, C, ldC, s);
     default: return launch_project_t<5>(E, N, k, ldE, S, M, ldS, C, ldC, s);
   }
 }

@@ -250,8 +250,12 @@ def test_greedy_deterministic(rb):
     assert torch.equal(a["E"], b["E"])
 
 
-@pytest.mark.parametrize("N,k,M", [(1000, 47, 2000), (777, 65, 1234), (64, 1, 1), (4, 130, 3), (10000, 3, 100)])
+@pytest.mark.parametrize("N,k,M", [(1000, 47, 2000), (777, 65, 1234), (64, 1, 1), (4, 130, 3), (10000, 3, 100),
+                                   (300, 161, 517), (300, 190, 700), (257, 224, 65), (300, 250, 129),
+                                   (300, 450, 70)])
 def test_project_matches_oracle(rb, N, k, M):
+    """Every block height (32 to 224 basis vectors) and several passes over
+    S for k > 224, with ragged tails in rows, columns and basis vectors."""
     E_host = ri.gaussian(50 + k, N, k)
     S_host = ri.gaussian(51 + M, N, M)
     C = rb.project(_dev(E_host), _dev(S_host)).cpu().numpy()  # (M, k)
