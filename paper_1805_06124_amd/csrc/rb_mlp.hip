@@ -2,8 +2,9 @@
 // layers din -> hidden -> hidden -> hidden -> dout, tanh hidden activations,
 // BF16 weights and activations, FP32 accumulation and FP32 master weights.
 // The hidden and output layers run on BF16 matrix cores
-// (v_mfma_f32_16x16x32_bf16); the first layer (din = 2) and the column sums
-// are vector kernels.
+// (v_mfma_f32_16x16x32_bf16), their bias gradients ride along in the
+// weight-gradient products; the first layer (din = 2) and its gradients are
+// vector kernels.
 //
 // Parameter layout (FP32 master and BF16 copy share offsets), row-major
 // [in][out]:  W1 (din x h), b1 (h), W2 (h x h), b2, W3 (h x h), b3,
@@ -30,57 +31,41 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // ---------------------------------------------------------------- GEMM --
 // C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak],
 // B(k, n) = B[k*sbk + n*sbn], BF16 operands, FP32 accumulation.
-// Block tile 64 x 64, 4 waves as 2 x 2 (32 x 32 each = 2 x 2 MFMA tiles),
-// K chunks of 32 staged in LDS as [row][k] so that each lane's 8 operand
-// values are one 16-byte read.
+// Block tile 64 x 64, 4 waves as 2 x 2 (32 x 32 each = 2 x 2 MFMA tiles).
+// K is staged in LDS as [row][k], so that each lane's 8 operand values are
+// one 16-byte read, kStage chunks of 32 at a time.  For the common layouts
+// the loads of a stage carry no branch: a thread issues all of them before
+// the first is stored, so one memory latency covers the stage rather than
+// one per chunk.
 // v_mfma_f32_16x16x32_bf16: A lane l holds A[l%16][8(l/16) .. +7],
 // B lane l holds B[8(l/16) .. +7][l%16], result lane l register r holds
 // D[4(l/16) + r][l%16].
 enum Epi { kEpiStore = 0, kEpiBiasTanh = 1, kEpiBias = 2, kEpiDTanh = 3 };
 
-constexpr int kGT = 64, kGK = 32, kGKP = kGK + 8;
+constexpr int kGT = 64, kGK = 32, kStage = 2, kGKP = kStage * kGK + 8;
 
-// Stage the 64 x 32 tile X(r0 + r, k0 + kk) = X[r*sr + k*sk] (r < 64,
-// kk < 32) into LDS as dst[r][kk].  vec: 1 = K contiguous (sk == 1), 2 = R
-// contiguous (sr == 1), with 16-byte aligned rows (one 16-byte load per
-// thread); 3 and 4 the same with 4-byte aligned rows (four 4-byte loads);
-// else 0 (scalar loads).  Each thread moves 8 values.
-__device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64_t sr, int64_t sk, int64_t R,
-                                           int64_t K, int64_t r0, int64_t k0, int vec, uint16_t (*dst)[kGKP],
-                                           int tid) {
-  if (vec == 1) {
-    const int r = tid >> 2, kk = (tid & 3) * 8;
-    const int64_t gr = r0 + r, gk = k0 + kk;
-    uint4 v = make_uint4(0, 0, 0, 0);
+// Operand layouts X(r, k) = X[r*sr + k*sk] for staging a 64 x 32 chunk
+// X(r0 + r, k0 + kk) into LDS as dst[r][kk]; each thread moves 8 values.
+// kK16, kK4: K contiguous (sk == 1) with 16- or 4-byte aligned rows; thread
+// t holds X(r0 + t/4, k0 + 8(t%4) + i).  kR16, kR4: R contiguous (sr == 1);
+// thread t holds X(r0 + 8(t%8) + i, k0 + t/8), i < 8.  kGen: any strides,
+// scalar loads.  Values outside the matrix are zero.
+enum Lay { kGen = 0, kK16 = 1, kR16 = 2, kK4 = 3, kR4 = 4 };
+
+// Guarded load of a chunk for a layout chosen at run time.
+__device__ __forceinline__ uint4 load_tile(const uint16_t* __restrict__ X, int64_t sr, int64_t sk, int64_t R,
+                                           int64_t K, int64_t r0, int64_t k0, int vec, int tid) {
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if (vec == kK16 || vec == kK4) {
+    const int64_t gr = r0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
     if (gr < R && gk + 7 < K) {
-      v = *reinterpret_cast<const uint4*>(X + gr * sr + gk);
-    } else if (gr < R) {
-      uint16_t t[8];
+      if (vec == kK16) {
+        return *reinterpret_cast<const uint4*>(X + gr * sr + gk);
+      } else {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gr * sr + gk);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = (gk + i < K) ? X[gr * sr + gk + i] : (uint16_t)0;
-      v = *reinterpret_cast<const uint4*>(t);
-    }
-    *reinterpret_cast<uint4*>(&dst[r][kk]) = v;
-  } else if (vec == 2) {
-    const int kk = tid >> 3, r = (tid & 7) * 8;
-    const int64_t gr = r0 + r, gk = k0 + kk;
-    uint16_t t[8];
-    if (gk < K && gr + 7 < R) {
-      *reinterpret_cast<uint4*>(t) = *reinterpret_cast<const uint4*>(X + gk * sk + gr);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = (gk < K && gr + i < R) ? X[gk * sk + gr + i] : (uint16_t)0;
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) dst[r + i][kk] = t[i];
-  } else if (vec == 3) {
-    const int r = tid >> 2, kk = (tid & 3) * 8;
-    const int64_t gr = r0 + r, gk = k0 + kk;
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (gr < R && gk + 7 < K) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gr * sr + gk);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) w[i] = src[i];
+        for (int i = 0; i < 4; ++i) w[i] = src[i];
+      }
     } else if (gr < R) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -89,42 +74,158 @@ __device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ X, int64
         w[i] = lo | (hi << 16);
       }
     }
-    *reinterpret_cast<uint4*>(&dst[r][kk]) = make_uint4(w[0], w[1], w[2], w[3]);
-  } else if (vec == 4) {
-    const int kk = tid >> 3, r = (tid & 7) * 8;
-    const int64_t gr = r0 + r, gk = k0 + kk;
+  } else if (vec == kR16 || vec == kR4) {
+    const int64_t gk = k0 + (tid >> 3), gr = r0 + (tid & 7) * 8;
     if (gk < K && gr + 7 < R) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gk * sk + gr);
+      if (vec == kR16) {
+        return *reinterpret_cast<const uint4*>(X + gk * sk + gr);
+      } else {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(X + gk * sk + gr);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = src[i];
+      }
+    } else if (gk < K) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t w = src[i];
-        dst[r + 2 * i][kk] = (uint16_t)(w & 0xffffu);
-        dst[r + 2 * i + 1][kk] = (uint16_t)(w >> 16);
+        const uint32_t lo = (gr + 2 * i < R) ? X[gk * sk + gr + 2 * i] : 0u;
+        const uint32_t hi = (gr + 2 * i + 1 < R) ? X[gk * sk + gr + 2 * i + 1] : 0u;
+        w[i] = lo | (hi << 16);
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) dst[r + i][kk] = (gk < K && gr + i < R) ? X[gk * sk + gr + i] : (uint16_t)0;
     }
   } else {
-    const int r = tid >> 2, kk = (tid & 3) * 8;
-    const int64_t gr = r0 + r;
+    const int64_t gr = r0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
+    if (gr < R) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t gk = k0 + kk + i;
-      dst[r][kk + i] = (gr < R && gk < K) ? X[gr * sr + gk * sk] : (uint16_t)0;
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = (gk + 2 * i < K) ? X[gr * sr + (gk + 2 * i) * sk] : 0u;
+        const uint32_t hi = (gk + 2 * i + 1 < K) ? X[gr * sr + (gk + 2 * i + 1) * sk] : 0u;
+        w[i] = lo | (hi << 16);
+      }
+    }
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 to_uint4(u32x4 v) { return make_uint4(v[0], v[1], v[2], v[3]); }
+
+// Branch-free load of a chunk for a layout fixed at compile time: the
+// address is clamped into the matrix and a value outside it replaced by zero
+// with a select (on whole 4-word vectors: a select of one loaded word on a
+// scalar condition is turned into a branch around the load by the compiler).  A thread's 8 values (kK16, kR16) or each pair of them
+// (kK4, kR4) lie wholly inside or wholly outside the matrix when the extent
+// along the contiguous direction is a multiple of 8 (K for kK16, R for kR16)
+// or of 2 (K for kK4, R for kR4); the host launches these layouts only then.
+template <int L>
+__device__ __forceinline__ uint4 load_fast(const uint16_t* __restrict__ X, int64_t sr, int64_t sk, int64_t R,
+                                           int64_t K, int64_t r0, int64_t k0, int tid) {
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  if (L == kK16 || L == kK4) {
+    const int64_t gr = r0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
+    const bool rok = gr < R;
+    const uint16_t* row = X + (rok ? gr : R - 1) * sr;
+    if (L == kK16) {
+      const bool ok = rok && gk < K;
+      const uint4 v = *reinterpret_cast<const uint4*>(row + (gk < K ? gk : K - 8));
+      return ok ? v : zero;
+    } else {
+      u32x4 x, keep;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t k = gk + 2 * i;
+        x[i] = *reinterpret_cast<const uint32_t*>(row + (k < K ? k : K - 2));
+        keep[i] = (rok && k < K) ? ~0u : 0u;
+      }
+      return to_uint4(x & keep);
+    }
+  } else {
+    const int64_t gk = k0 + (tid >> 3), gr = r0 + (tid & 7) * 8;
+    const bool kok = gk < K;
+    const uint16_t* col = X + (kok ? gk : K - 1) * sk;
+    if (L == kR16) {
+      const bool ok = kok && gr < R;
+      const uint4 v = *reinterpret_cast<const uint4*>(col + (gr < R ? gr : R - 8));
+      return ok ? v : zero;
+    } else {
+      u32x4 x, keep;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = gr + 2 * i;
+        x[i] = *reinterpret_cast<const uint32_t*>(col + (r < R ? r : R - 2));
+        keep[i] = (kok && r < R) ? ~0u : 0u;
+      }
+      return to_uint4(x & keep);
     }
   }
 }
 
-// Split over K (kEpiStore only): workgroup z reduces k in [z kc, (z+1) kc)
-// and stores its partial product at C + z cz; one split is kc = K, cz = 0.
-template <int kEpi>
+// LDS placement of tile element (r, c): the 8-wide column group is XORed
+// with (r / 8) % 8, so that the rows 8 apart written by one store
+// instruction of the R-contiguous layouts fall in different banks (with
+// 16-byte aligned rows they would share one); the row pad keeps adjacent
+// rows in different banks for the operand reads.  Needs an even kStage.
+static_assert(kStage % 2 == 0, "the swizzle permutes groups within blocks of 8");
+__device__ __forceinline__ int swz(int r, int c) { return (((c >> 3) ^ ((r >> 3) & 7)) << 3) | (c & 7); }
+
+// writes a thread's values of a chunk to column koff of dst; rowwise says
+// whether they run along R (kR16, kR4) or along K (the other layouts)
+__device__ __forceinline__ void store_tile(uint4 v, bool rowwise, uint16_t (*dst)[kGKP], int koff, int tid) {
+  if (rowwise) {
+    const int kk = koff + (tid >> 3), r = (tid & 7) * 8;
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dst[r + 2 * i][swz(r, kk)] = (uint16_t)(w[i] & 0xffffu);
+      dst[r + 2 * i + 1][swz(r, kk)] = (uint16_t)(w[i] >> 16);
+    }
+  } else {
+    *reinterpret_cast<uint4*>(&dst[tid >> 2][swz(tid >> 2, koff + (tid & 3) * 8)]) = v;
+  }
+}
+
+// one K chunk of 32 at column ko of the staged tiles: 2 x 2 MFMA tiles per wave
+__device__ __forceinline__ void mma_chunk(const uint16_t (*sA)[kGKP], const uint16_t (*sB)[kGKP], int ko, int lane,
+                                          int wm, int wn, f4v (&acc)[2][2]) {
+  bf16x8 a[2], b[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int ra = wm * 32 + 16 * t + (lane & 15), rb = wn * 32 + 16 * t + (lane & 15);
+    a[t] = *reinterpret_cast<const bf16x8*>(&sA[ra][swz(ra, ko + 8 * (lane >> 4))]);
+    b[t] = *reinterpret_cast<const bf16x8*>(&sB[rb][swz(rb, ko + 8 * (lane >> 4))]);
+  }
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+      acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+}
+
+// thread (n = tid / 4, q = tid % 4) adds sB[n][ko + 8q .. ko + 8q + 7]
+__device__ __forceinline__ void colsum_chunk(const uint16_t (*sB)[kGKP], int ko, int tid, float& cs) {
+  const uint4 w = *reinterpret_cast<const uint4*>(&sB[tid >> 2][swz(tid >> 2, ko + 8 * (tid & 3))]);
+  const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cs += __uint_as_float(u[i] << 16);
+    cs += __uint_as_float(u[i] & 0xffff0000u);
+  }
+}
+
+// LA, LB: the layouts of A (as X(m, k)) and B (as X(n, k)), or kGen for
+// layouts passed at run time in vecA, vecB (guarded loads, one chunk at a
+// time).  Split over K (kEpiStore only): workgroup z reduces k in
+// [z kc, (z+1) kc) and stores its partial product at C + z cz; one split is
+// kc = K, cz = 0.  With csum set (kEpiStore only), the workgroups of the
+// first row of tiles also add up the columns of B over their K range, from
+// the staged tiles, and store them as row M of C: C(M, n) = sum_k B(k, n).
+// That is the bias gradient beside a weight gradient dW = H^T dZ.
+template <int kEpi, int LA, int LB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
                                                    int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
                                                    int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ Cb,
                                                    int64_t ldcb, const uint16_t* __restrict__ H, int64_t ldh,
-                                                   int vecA, int vecB, int64_t kc, int64_t cz) {
+                                                   int vecA, int vecB, int64_t kc, int64_t cz, int csum) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
   __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -139,22 +240,71 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t
   const int64_t kb = (int64_t)blockIdx.z * kc;
   const int64_t ke = (kb + kc < K) ? kb + kc : K;
   if (kEpi == kEpiStore) C += (int64_t)blockIdx.z * cz;
-  for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
-    stage_tile(A, sam, sak, M, ke, m0, k0, vecA, sA, tid);
-    stage_tile(B, sbn, sbk, N, ke, n0, k0, vecB, sB, tid);
-    __syncthreads();
-    bf16x8 a[2], b[2];
+  const bool do_csum = kEpi == kEpiStore && csum && blockIdx.y == 0;
+  float cs = 0.f;
+  // the epilogue's operands (bias, or the activations for the tanh
+  // derivative) do not depend on the product: load them first, from clamped
+  // addresses, so that their latency overlaps the main loop's
+  float bv[2] = {0.f, 0.f};
+  float hv[2][2][4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = *reinterpret_cast<const bf16x8*>(&sA[wm * 32 + 16 * t + (lane & 15)][8 * (lane >> 4)]);
-      b[t] = *reinterpret_cast<const bf16x8*>(&sB[wn * 32 + 16 * t + (lane & 15)][8 * (lane >> 4)]);
-    }
+  for (int tb = 0; tb < 2; ++tb) {
+    const int64_t n = n0 + wn * 32 + 16 * tb + (lane & 15);
+    const int64_t nc = n < N ? n : N - 1;
+    if (kEpi == kEpiBiasTanh || kEpi == kEpiBias) bv[tb] = bias[nc];
 #pragma unroll
     for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
-      for (int tb = 0; tb < 2; ++tb)
-        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 32 + 16 * ta + 4 * (lane >> 4) + r;
+        hv[ta][tb][r] = kEpi == kEpiDTanh ? bf2f(H[(m < M ? m : M - 1) * ldh + nc]) : 0.f;
+      }
+  }
+  for (int64_t k0 = kb; k0 < ke; k0 += kStage * kGK) {
+    const int64_t left = (ke - k0 + kGK - 1) / kGK;
+    const int nsub = left < kStage ? (int)left : kStage;
+    if (LA != kGen && LB != kGen) {
+      // chunks past ke load clamped addresses and hold zeros
+      uint4 ra[kStage], rb[kStage];
+#pragma unroll
+      for (int c = 0; c < kStage; ++c) {
+        ra[c] = load_fast<LA>(A, sam, sak, M, ke, m0, k0 + c * kGK, tid);
+        rb[c] = load_fast<LB>(B, sbn, sbk, N, ke, n0, k0 + c * kGK, tid);
+      }
+#pragma unroll
+      for (int c = 0; c < kStage; ++c) {
+        store_tile(ra[c], LA == kR16 || LA == kR4, sA, c * kGK, tid);
+        store_tile(rb[c], LB == kR16 || LB == kR4, sB, c * kGK, tid);
+      }
+    } else {
+      for (int c = 0; c < nsub; ++c) {
+        store_tile(load_tile(A, sam, sak, M, ke, m0, k0 + c * kGK, vecA, tid), vecA == kR16 || vecA == kR4, sA,
+                   c * kGK, tid);
+        store_tile(load_tile(B, sbn, sbk, N, ke, n0, k0 + c * kGK, vecB, tid), vecB == kR16 || vecB == kR4, sB,
+                   c * kGK, tid);
+      }
+    }
     __syncthreads();
+    if (nsub == kStage) {
+#pragma unroll
+      for (int c = 0; c < kStage; ++c) {
+        if (do_csum) colsum_chunk(sB, c * kGK, tid, cs);
+        mma_chunk(sA, sB, c * kGK, lane, wm, wn, acc);
+      }
+    } else {
+      for (int c = 0; c < nsub; ++c) {
+        if (do_csum) colsum_chunk(sB, c * kGK, tid, cs);
+        mma_chunk(sA, sB, c * kGK, lane, wm, wn, acc);
+      }
+    }
+    __syncthreads();
+  }
+  if (do_csum) {
+    // the four partial sums of a column sit in adjacent lanes; (q0 + q1) + (q2 + q3)
+    cs += __shfl_xor(cs, 1, 64);
+    cs += __shfl_xor(cs, 2, 64);
+    const int64_t n = n0 + (tid >> 2);
+    if ((tid & 3) == 0 && n < N) C[M * ldc + n] = cs;
   }
 #pragma unroll
   for (int ta = 0; ta < 2; ++ta)
@@ -169,11 +319,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t
         if (kEpi == kEpiStore) {
           C[m * ldc + n] = v;
         } else if (kEpi == kEpiBiasTanh) {
-          Cb[m * ldcb + n] = f2bf(tanhf(v + bias[n]));
+          Cb[m * ldcb + n] = f2bf(tanhf(v + bv[tb]));
         } else if (kEpi == kEpiBias) {
-          C[m * ldc + n] = v + bias[n];
+          C[m * ldc + n] = v + bv[tb];
         } else {
-          const float h = bf2f(H[m * ldh + n]);
+          const float h = hv[ta][tb][r];
           Cb[m * ldcb + n] = f2bf(v * (1.f - h * h));
         }
       }
@@ -193,46 +343,60 @@ __global__ __launch_bounds__(256) void k_layer1_fwd(const float* __restrict__ X,
 }
 
 // column sums over the batch of a BF16 matrix D (B x d): db[o] = sum_b D[b][o]
-// and, if X is given, dW[i][o] = sum_b X[b][i] D[b][o] (i < din).  Partial
-// sums per workgroup row chunk go to part[(chunk)(din+1) d], reduced by
-// k_colsum_final in a fixed order.
+// and, if X is given, dW[i][o] = sum_b X[b][i] D[b][o] (i < din <= 4).
+// Partial sums per workgroup row chunk go to part[(chunk)(din+1) d], reduced
+// by k_colsum_final in a fixed order.  The row loads of a chunk carry no
+// branch (clamped row, zero by select), so they are all in flight together.
 constexpr int kColRows = 32;
 __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ D, int64_t B, int d,
                                                 const float* __restrict__ X, int din, float* __restrict__ part) {
   const int o = blockIdx.x * 256 + threadIdx.x;
   if (o >= d) return;
   const int64_t b0 = (int64_t)blockIdx.y * kColRows;
-  const int64_t b1 = (b0 + kColRows < B) ? b0 + kColRows : B;
-  const int nx = X ? din : 0;
-  float s = 0.f, sx[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t b = b0; b < b1; ++b) {
-    const float v = bf2f(D[b * d + o]);
-    s += v;
-    for (int i = 0; i < nx; ++i) sx[i] += X[b * din + i] * v;
+  const int nb = (B - b0 < kColRows) ? (int)(B - b0) : kColRows;
+  float v[kColRows];
+#pragma unroll
+  for (int r = 0; r < kColRows; ++r) {
+    const float x = bf2f(D[(b0 + (r < nb ? r : nb - 1)) * d + o]);
+    v[r] = r < nb ? x : 0.f;
   }
-  float* p = part + (int64_t)blockIdx.y * (nx + 1) * d;
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < kColRows; ++r) s += v[r];
+  float* p = part + (int64_t)blockIdx.y * ((X ? din : 0) + 1) * d;
   p[o] = s;
-  for (int i = 0; i < nx; ++i) p[(int64_t)(i + 1) * d + o] = sx[i];
+  if (!X) return;
+  for (int i = 0; i < din; ++i) {
+    float xv[kColRows];
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) xv[r] = X[(b0 + (r < nb ? r : nb - 1)) * din + i];
+    float sx = 0.f;
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) sx += xv[r] * v[r];
+    p[(int64_t)(i + 1) * d + o] = sx;
+  }
 }
-// the partial sums of k_colsum added per output: 64 outputs per workgroup,
-// four threads per output each adding every fourth chunk, the four sums
-// then added in a fixed order
+// the partial sums of k_colsum added per output: 16 outputs per workgroup,
+// 16 lanes per output each adding every 16th chunk, the 16 sums then added
+// in a fixed butterfly order (every lane ends with the same value)
 __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int64_t chunks, int64_t len,
                                                       float* __restrict__ db, float* __restrict__ dW, int d) {
-  __shared__ float sred[4][64];
-  const int ol = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t t = (int64_t)blockIdx.x * 64 + ol;
+  const int q = threadIdx.x & 15;
+  const int64_t t = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   float s = 0.f;
-  if (t < len)
-    for (int64_t c = q; c < chunks; c += 4) s += part[c * len + t];
-  sred[q][ol] = s;
-  __syncthreads();
+  if (t < len) {
+#pragma unroll 8
+    for (int64_t c = q; c < chunks; c += 16) s += part[c * len + t];
+  }
+  s += __shfl_xor(s, 8, 64);
+  s += __shfl_xor(s, 4, 64);
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 1, 64);
   if (q == 0 && t < len) {
-    const float v = (sred[0][ol] + sred[1][ol]) + (sred[2][ol] + sred[3][ol]);
     if (t < d)
-      db[t] = v;
+      db[t] = s;
     else
-      dW[t - d] = v;
+      dW[t - d] = s;
   }
 }
 
@@ -242,6 +406,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= len) return;
   float s = 0.f;
+#pragma unroll 16
   for (int z = 0; z < splits; ++z) s += P[(int64_t)z * len + t];
   C[t] = s;
 }
@@ -339,15 +504,74 @@ __global__ __launch_bounds__(256) void k_coef_relerr(const float* __restrict__ Y
   if (lane == 0) out[j] = den > 0.0 ? sqrt(num / den) : sqrt(num);
 }
 
-// vector-load mode of an operand X(r, k) = X[r*sr + k*sk] (see stage_tile)
+// layout of an operand X(r, k) = X[r*sr + k*sk] (see Lay)
 int vec_mode(const uint16_t* X, int64_t sr, int64_t sk) {
   const bool al = (reinterpret_cast<uintptr_t>(X) & 15) == 0;
-  if (al && sk == 1 && (sr * 2) % 16 == 0) return 1;
-  if (al && sr == 1 && (sk * 2) % 16 == 0) return 2;
+  if (al && sk == 1 && (sr * 2) % 16 == 0) return kK16;
+  if (al && sr == 1 && (sk * 2) % 16 == 0) return kR16;
   const bool al4 = (reinterpret_cast<uintptr_t>(X) & 3) == 0;
-  if (al4 && sk == 1 && sr % 2 == 0) return 3;
-  if (al4 && sr == 1 && sk % 2 == 0) return 4;
-  return 0;
+  if (al4 && sk == 1 && sr % 2 == 0) return kK4;
+  if (al4 && sr == 1 && sk % 2 == 0) return kR4;
+  return kGen;
+}
+
+// the layout load_fast may use for an operand of layout vec with R rows and
+// reduction length K (see load_fast), else kGen
+int fast_layout(int vec, int64_t R, int64_t K) {
+  switch (vec) {
+    case kK16: return K % 8 == 0 ? kK16 : (K % 2 == 0 ? kK4 : kGen);
+    case kK4: return K % 2 == 0 ? kK4 : kGen;
+    case kR16: return R % 8 == 0 ? kR16 : (R % 2 == 0 ? kR4 : kGen);
+    case kR4: return R % 2 == 0 ? kR4 : kGen;
+    default: return kGen;
+  }
+}
+
+struct GemmArgs {
+  int64_t M, N, K;
+  const uint16_t* A;
+  int64_t sam, sak;
+  const uint16_t* B;
+  int64_t sbk, sbn;
+  float* C;
+  int64_t ldc;
+  const float* bias;
+  uint16_t* Cb;
+  int64_t ldcb;
+  const uint16_t* H;
+  int64_t ldh;
+  int64_t kc, cz;
+  int csum;
+};
+
+template <int kEpi, int LA, int LB>
+void launch_gemm(dim3 grid, const GemmArgs& g, int vecA, int vecB, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_bf16<kEpi, LA, LB>), grid, dim3(256), 0, s, g.M, g.N, g.K, g.A, g.sam, g.sak, g.B, g.sbk,
+                     g.sbn, g.C, g.ldc, g.bias, g.Cb, g.ldcb, g.H, g.ldh, vecA, vecB, g.kc, g.cz, g.csum);
+}
+
+// Launches the instantiation for the operands' layouts.  Each product of the
+// MLP has a fixed orientation: the forward products read A along K and B
+// along R, the products with transposed weights read both along K, the
+// weight gradients both along R; other layouts take the guarded kernel.
+template <int kEpi>
+hipError_t launch_layouts(dim3 grid, const GemmArgs& g, hipStream_t s) {
+  const int vecA = vec_mode(g.A, g.sam, g.sak), vecB = vec_mode(g.B, g.sbn, g.sbk);
+  const int la = fast_layout(vecA, g.M, g.K), lb = fast_layout(vecB, g.N, g.K);
+  constexpr bool kRA = kEpi == kEpiStore, kRB = kEpi != kEpiDTanh;
+  constexpr int a16 = kRA ? kR16 : kK16, a4 = kRA ? kR4 : kK4;
+  constexpr int b16 = kRB ? kR16 : kK16, b4 = kRB ? kR4 : kK4;
+  if (la == a16 && lb == b16)
+    launch_gemm<kEpi, a16, b16>(grid, g, vecA, vecB, s);
+  else if (la == a16 && lb == b4)
+    launch_gemm<kEpi, a16, b4>(grid, g, vecA, vecB, s);
+  else if (la == a4 && lb == b16)
+    launch_gemm<kEpi, a4, b16>(grid, g, vecA, vecB, s);
+  else if (la == a4 && lb == b4)
+    launch_gemm<kEpi, a4, b4>(grid, g, vecA, vecB, s);
+  else
+    launch_gemm<kEpi, kGen, kGen>(grid, g, vecA, vecB, s);
+  return hipGetLastError();
 }
 
 template <int kEpi>
@@ -356,15 +580,14 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam,
                 const uint16_t* H, int64_t ldh, hipStream_t s) {
   dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT));
   if (grid.y > 65535) return hipErrorInvalidValue;
-  const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
-  hipLaunchKernelGGL(k_gemm_bf16<kEpi>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Cb,
-                     ldcb, H, ldh, vecA, vecB, K, (int64_t)0);
-  return hipGetLastError();
+  const GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Cb, ldcb, H, ldh, K, 0, 0};
+  return launch_layouts<kEpi>(grid, g, s);
 }
 
-// Weight gradients C (M x N, ldc = N) = A B with a long reduction K (the
-// batch): kSplitK workgroups per output tile each reduce a K range of at
-// least kSplitMin into P (kSplitK x M x N floats), then the splits are added
+// Weight gradient C (M x N, ldc = N) = A B with a long reduction K (the
+// batch) and, directly after it, the bias gradient C(M, n) = sum_k B(k, n):
+// kSplitK workgroups per output tile each reduce a K range of at least
+// kSplitMin into P (kSplitK x (M + 1) x N floats), then the splits are added
 // in a fixed order.
 constexpr int kSplitK = 16;
 constexpr int64_t kSplitMin = 128;
@@ -377,12 +600,11 @@ hipError_t gemm_splitk(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64
   splits = (int)((K + kc - 1) / kc);
   dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT), (unsigned)splits);
   if (grid.y > 65535) return hipErrorInvalidValue;
-  const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
-  hipLaunchKernelGGL(k_gemm_bf16<kEpiStore>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, P, N,
-                     nullptr, nullptr, 0, nullptr, 0, vecA, vecB, kc, M * N);
-  hipError_t e = hipGetLastError();
+  const int64_t len = (M + 1) * N;
+  const GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, P, N, nullptr, nullptr, 0, nullptr, 0, kc, len, 1};
+  hipError_t e = launch_layouts<kEpiStore>(grid, g, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, P, splits, M * N, C);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, P, splits, len, C);
   return hipGetLastError();
 }
 
@@ -409,7 +631,7 @@ hipError_t colsum(const uint16_t* D, int64_t B, int d, const float* X, int din, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t len = (int64_t)((X ? din : 0) + 1) * d;
-  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 63) / 64)), dim3(256), 0, s, part, chunks, len, db, dW,
+  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, part, chunks, len, db, dW,
                      d);
   return hipGetLastError();
 }
@@ -431,7 +653,7 @@ size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
   if (batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return 0;
   const int64_t chunks = (batch + kColRows - 1) / kColRows;
   const int64_t part = chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout);
-  const int64_t splitk = (int64_t)kSplitK * hidden * (hidden > dout ? hidden : dout);
+  const int64_t splitk = (int64_t)kSplitK * (hidden + 1) * (hidden > dout ? hidden : dout);
   // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums (column sums,
   // then the split-K partials of the weight gradients)
   return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout) * 2 + (size_t)batch * dout * 4 +
@@ -515,19 +737,18 @@ int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, 
   float *Yw, *part, *splitp;
   carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp);
   if (dY_in) dY = const_cast<uint16_t*>(dY_in);
+  // Each bias directly follows its weight matrix in the layout (b_l = W_l +
+  // rows x cols), so one split-K call writes dW_l and db_l = colsum(dZ_l).
   // output layer: dW4 = H3^T dY, db4 = colsum(dY), dZ3 = (dY W4^T) * (1 - H3^2)
   RB_HIP(gemm_splitk(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, grad + L.W4, splitp, stream));
-  RB_HIP(colsum(dY, batch, dout, nullptr, din, part, grad + L.b4, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, dout, dY, dout, 1, p16 + L.W4, 1, dout, nullptr, 0, nullptr, dz[0], hidden,
                          H[2], hidden, stream));
   // hidden layer 3: dW3 = H2^T dZ3, db3, dZ2 = (dZ3 W3^T) * (1 - H2^2)
   RB_HIP(gemm_splitk(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, grad + L.W3, splitp, stream));
-  RB_HIP(colsum(dz[0], batch, hidden, nullptr, din, part, grad + L.b3, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[0], hidden, 1, p16 + L.W3, 1, hidden, nullptr, 0, nullptr, dz[1],
                          hidden, H[1], hidden, stream));
   // hidden layer 2: dW2 = H1^T dZ2, db2, dZ1 = (dZ2 W2^T) * (1 - H1^2)
   RB_HIP(gemm_splitk(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, grad + L.W2, splitp, stream));
-  RB_HIP(colsum(dz[1], batch, hidden, nullptr, din, part, grad + L.b2, nullptr, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[1], hidden, 1, p16 + L.W2, 1, hidden, nullptr, 0, nullptr, dz[0],
                          hidden, H[0], hidden, stream));
   // first layer: dW1 = X^T dZ1, db1 = colsum(dZ1)

@@ -18,35 +18,41 @@ from oracle import mlp
 pytestmark = pytest.mark.gpu
 
 
-def _setup(rb, k=47, B=300, seed=7):
+def _setup(rb, k=47, B=300, seed=7, h=256):
     from paper_1805_06124_amd.surrogate import Surrogate
-    din, h, dout = 2, 256, 2 * k
+    din, dout = 2, 2 * k
     p = ri.mlp_init(seed, din, h, dout)
     rng = np.random.default_rng(seed)
     lay = ri.mlp_layout(din, h, dout)
     for b in ("b1", "b2", "b3", "b4"):
         o, n = lay[b]
         p[o:o + n] = 0.1 * rng.standard_normal(n).astype(np.float32)
-    sur = Surrogate(k, p, ranges=(20.0, 60.0, 1.0, 4.0), batch=B)
+    sur = Surrogate(k, p, ranges=(20.0, 60.0, 1.0, 4.0), hidden=h, batch=B)
     X = rng.uniform(-1, 1, (B, din)).astype(np.float32)
     T = (0.3 * rng.standard_normal((B, dout))).astype(np.float32)
     return sur, p, X, T, (din, h, dout)
 
 
-def test_forward_matches_oracle(rb):
-    sur, p, X, T, (din, h, dout) = _setup(rb)
+# hidden 256: the 16-byte branch-free staging; 100: rows of 200 bytes, the
+# 4-byte branch-free staging with a reduction length not a multiple of 8;
+# 37: odd rows, every product through the guarded kernel
+@pytest.mark.parametrize("h", [256, 100, 37])
+def test_forward_matches_oracle(rb, h):
+    sur, p, X, T, (din, h, dout) = _setup(rb, h=h)
     Y = sur.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     Yr, _ = mlp.forward(p, X, din, h, dout, bf16_round=True)
     assert np.linalg.norm(Y - Yr) <= 1e-2 * np.linalg.norm(Yr)
     assert np.max(np.abs(Y - Yr)) <= 4 * 2 ** -8 * np.max(np.abs(Yr))
 
 
-@pytest.mark.parametrize("k,B", [(47, 300), (141, 4096)])
-def test_gradients_match_oracle(rb, k, B):
+@pytest.mark.parametrize("k,B,h", [(47, 300, 256), (141, 4096, 256), (23, 130, 100), (47, 300, 37)])
+def test_gradients_match_oracle(rb, k, B, h):
     """Also at the training shape (k = 141, batch 4,096): 16 splits of the
-    batch reduction for the weight gradients, 128 column-sum chunks, and
-    output rows 2k = 282 wide (4-byte aligned staging)."""
-    sur, p, X, T, (din, h, dout) = _setup(rb, k=k, B=B)
+    batch reduction for the weight gradients (with the bias gradients as
+    their extra row), 128 column-sum chunks for the first layer, and output
+    rows 2k = 282 wide (4-byte aligned staging).  Hidden widths 100 and 37
+    take the 4-byte and the guarded staging, with ragged tiles."""
+    sur, p, X, T, (din, h, dout) = _setup(rb, k=k, B=B, h=h)
     Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
     Y = sur.forward(Xd)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
