@@ -584,28 +584,32 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam,
   return launch_layouts<kEpi>(grid, g, s);
 }
 
-// Weight gradient C (M x N, ldc = N) = A B with a long reduction K (the
-// batch) and, directly after it, the bias gradient C(M, n) = sum_k B(k, n):
-// kSplitK workgroups per output tile each reduce a K range of at least
-// kSplitMin into P (kSplitK x (M + 1) x N floats), then the splits are added
-// in a fixed order.
+// Weight gradients with a long reduction K (the batch): kSplitK workgroups
+// per output tile each reduce a K range of at least kSplitMin (whole staging
+// chunks); the partial sums of split z of every product go to P + z cz, and
+// one k_splitk_reduce adds the splits of all of them in a fixed order.
 constexpr int kSplitK = 16;
 constexpr int64_t kSplitMin = 128;
-hipError_t gemm_splitk(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam, int64_t sak,
-                       const uint16_t* B, int64_t sbk, int64_t sbn, float* C, float* P, hipStream_t s) {
+int64_t splitk_chunk(int64_t K, int* splits_out) {
   int splits = kSplitK;
   while (splits > 1 && (K + splits - 1) / splits < kSplitMin) splits /= 2;
   int64_t kc = (K + splits - 1) / splits;
-  kc = (kc + kGK - 1) / kGK * kGK;  // whole staging chunks
-  splits = (int)((K + kc - 1) / kc);
+  kc = (kc + kGK - 1) / kGK * kGK;
+  *splits_out = (int)((K + kc - 1) / kc);
+  return kc;
+}
+
+// Partial products of C (M x N, row-major) = A B over each split of K, and
+// below them the bias gradient C(M, n) = sum_k B(k, n): split z writes the
+// (M + 1) x N block at P + z cz.
+hipError_t gemm_splitk_partial(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam, int64_t sak,
+                               const uint16_t* B, int64_t sbk, int64_t sbn, float* P, int64_t cz, hipStream_t s) {
+  int splits;
+  const int64_t kc = splitk_chunk(K, &splits);
   dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT), (unsigned)splits);
   if (grid.y > 65535) return hipErrorInvalidValue;
-  const int64_t len = (M + 1) * N;
-  const GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, P, N, nullptr, nullptr, 0, nullptr, 0, kc, len, 1};
-  hipError_t e = launch_layouts<kEpiStore>(grid, g, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, P, splits, len, C);
-  return hipGetLastError();
+  const GemmArgs g{M, N, K, A, sam, sak, B, sbk, sbn, P, N, nullptr, nullptr, 0, nullptr, 0, kc, cz, 1};
+  return launch_layouts<kEpiStore>(grid, g, s);
 }
 
 struct Layout {
@@ -653,7 +657,8 @@ size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
   if (batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return 0;
   const int64_t chunks = (batch + kColRows - 1) / kColRows;
   const int64_t part = chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout);
-  const int64_t splitk = (int64_t)kSplitK * (hidden + 1) * (hidden > dout ? hidden : dout);
+  // split-K partials of [dW2 db2 dW3 db3 dW4 db4], one contiguous block
+  const int64_t splitk = (int64_t)kSplitK * ((int64_t)(hidden + 1) * (2 * hidden + dout));
   // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums (column sums,
   // then the split-K partials of the weight gradients)
   return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout) * 2 + (size_t)batch * dout * 4 +
@@ -738,19 +743,30 @@ int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, 
   carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp);
   if (dY_in) dY = const_cast<uint16_t*>(dY_in);
   // Each bias directly follows its weight matrix in the layout (b_l = W_l +
-  // rows x cols), so one split-K call writes dW_l and db_l = colsum(dZ_l).
+  // rows x cols), and W2 b2 W3 b3 W4 b4 are one contiguous range: the three
+  // split-K products write their partials (dW_l with db_l = colsum(dZ_l)
+  // below it) into one block laid out like that range, and one reduction
+  // adds the splits of all three into grad.
+  const int64_t lenW = L.b4 + dout - L.W2;
+  int splits;
+  (void)splitk_chunk(batch, &splits);
   // output layer: dW4 = H3^T dY, db4 = colsum(dY), dZ3 = (dY W4^T) * (1 - H3^2)
-  RB_HIP(gemm_splitk(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, grad + L.W4, splitp, stream));
+  RB_HIP(gemm_splitk_partial(hidden, dout, batch, H[2], 1, hidden, dY, dout, 1, splitp + (L.W4 - L.W2), lenW,
+                             stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, dout, dY, dout, 1, p16 + L.W4, 1, dout, nullptr, 0, nullptr, dz[0], hidden,
                          H[2], hidden, stream));
   // hidden layer 3: dW3 = H2^T dZ3, db3, dZ2 = (dZ3 W3^T) * (1 - H2^2)
-  RB_HIP(gemm_splitk(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, grad + L.W3, splitp, stream));
+  RB_HIP(gemm_splitk_partial(hidden, hidden, batch, H[1], 1, hidden, dz[0], hidden, 1, splitp + (L.W3 - L.W2), lenW,
+                             stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[0], hidden, 1, p16 + L.W3, 1, hidden, nullptr, 0, nullptr, dz[1],
                          hidden, H[1], hidden, stream));
   // hidden layer 2: dW2 = H1^T dZ2, db2, dZ1 = (dZ2 W2^T) * (1 - H1^2)
-  RB_HIP(gemm_splitk(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, grad + L.W2, splitp, stream));
+  RB_HIP(gemm_splitk_partial(hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, splitp, lenW, stream));
   RB_HIP(gemm<kEpiDTanh>(batch, hidden, hidden, dz[1], hidden, 1, p16 + L.W2, 1, hidden, nullptr, 0, nullptr, dz[0],
                          hidden, H[0], hidden, stream));
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((lenW + 255) / 256)), dim3(256), 0, stream, splitp, splits,
+                     lenW, grad + L.W2);
+  RB_HIP(hipGetLastError());
   // first layer: dW1 = X^T dZ1, db1 = colsum(dZ1)
   RB_HIP(colsum(dz[0], batch, hidden, X, din, part, grad + L.b1, grad + L.W1, stream));
   return RB_OK;
