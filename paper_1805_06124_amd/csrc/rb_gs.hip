@@ -23,7 +23,22 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
   for (int64_t r = 0; r < nv; ++r) {
     const double2* v = V + r * ldV;
     double re = 0.0, im = 0.0;
-    for (int64_t n = threadIdx.x; n < N; n += kGsThreads) {
+    // eight rows per thread in flight, added in the order of n
+    int64_t n = threadIdx.x;
+    for (; n + 7 * kGsThreads < N; n += 8 * kGsThreads) {
+      double2 a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = e[n + u * kGsThreads];
+        b[u] = v[n + u * kGsThreads];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        re += a[u].x * b[u].x + a[u].y * b[u].y;
+        im += a[u].x * b[u].y - a[u].y * b[u].x;
+      }
+    }
+    for (; n < N; n += kGsThreads) {
       double2 a = e[n], b = v[n];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
@@ -47,18 +62,20 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
   }
 }
 
-// V[n + r*ldV] -= sum_i E[n + i*ldE] G[i + r*k]; one thread per row n.
-__global__ __launch_bounds__(kGsThreads) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
-                                                           const double2* __restrict__ G, double2* __restrict__ V,
-                                                           int64_t ldV, int64_t nv, int64_t N) {
-  const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+// V[n + r*ldV] -= sum_i E[n + i*ldE] G[i + r*k]; one thread per row n,
+// one wave per workgroup (the grid spreads over more compute units), eight
+// basis vectors per thread in flight, added in the order of i.
+constexpr int kSubThreads = 64;
+__global__ __launch_bounds__(kSubThreads) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
+                                                            const double2* __restrict__ G, double2* __restrict__ V,
+                                                            int64_t ldV, int64_t nv, int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * kSubThreads + threadIdx.x;
   if (n >= N) return;
   constexpr int kMaxNv = 8;
   double re[kMaxNv], im[kMaxNv];
 #pragma unroll
   for (int r = 0; r < kMaxNv; ++r) re[r] = im[r] = 0.0;
-  for (int64_t i = 0; i < k; ++i) {
-    double2 a = E[n + i * ldE];
+  auto add = [&](const double2 a, int64_t i) {
 #pragma unroll
     for (int r = 0; r < kMaxNv; ++r) {
       if (r < nv) {
@@ -67,7 +84,16 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_n_sub(const double2* __rest
         im[r] += a.x * g.y + a.y * g.x;
       }
     }
+  };
+  int64_t i = 0;
+  for (; i + 8 <= k; i += 8) {
+    double2 a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = E[n + (i + u) * ldE];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) add(a[u], i + u);
   }
+  for (; i < k; ++i) add(E[n + i * ldE], i);
 #pragma unroll
   for (int r = 0; r < kMaxNv; ++r) {
     if (r < nv) {
@@ -123,8 +149,8 @@ hipError_t launch_gemv_n_sub(const double2* E, int64_t ldE, int64_t k, const dou
                              int64_t nv, int64_t N, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (nv > 8) return hipErrorInvalidValue;
-  int64_t grid = (N + kGsThreads - 1) / kGsThreads;
-  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)grid), dim3(kGsThreads), 0, s, E, ldE, k, G, V, ldV, nv, N);
+  int64_t grid = (N + kSubThreads - 1) / kSubThreads;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)grid), dim3(kSubThreads), 0, s, E, ldE, k, G, V, ldV, nv, N);
   return hipGetLastError();
 }
 
