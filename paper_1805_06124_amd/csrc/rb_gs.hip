@@ -20,6 +20,48 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
   const double2* e = E + i * ldE;
   __shared__ double sre[kGsThreads / 64], sim[kGsThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (nv > 1) {
+    // several vectors (at most kMaxV): e_i is read once for all of them;
+    // each vector's sum is formed in the same order as below
+    constexpr int kMaxV = 8;
+    __shared__ double mre[kGsThreads / 64][kMaxV], mim[kGsThreads / 64][kMaxV];
+    double re[kMaxV], im[kMaxV];
+#pragma unroll
+    for (int r = 0; r < kMaxV; ++r) re[r] = im[r] = 0.0;
+    for (int64_t n = threadIdx.x; n < N; n += kGsThreads) {
+      const double2 a = e[n];
+      double2 b[kMaxV];
+      // vectors past nv read the last one (valid memory) and are not added
+#pragma unroll
+      for (int r = 0; r < kMaxV; ++r) b[r] = V[n + (r < nv ? r : nv - 1) * ldV];
+#pragma unroll
+      for (int r = 0; r < kMaxV; ++r) {
+        if (r < nv) {
+          re[r] += a.x * b[r].x + a.y * b[r].y;
+          im[r] += a.x * b[r].y - a.y * b[r].x;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxV; ++r) {
+      const double wr = wave_sum(re[r]), wi = wave_sum(im[r]);
+      if (lane == 0) {
+        mre[wave][r] = wr;
+        mim[wave][r] = wi;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+      const int r = threadIdx.x;
+      double tr = 0.0, ti = 0.0;
+      for (int w = 0; w < kGsThreads / 64; ++w) {
+        tr += mre[w][r];
+        ti += mim[w][r];
+      }
+      G[i + r * k] = make_double2(tr, ti);
+    }
+    return;
+  }
   for (int64_t r = 0; r < nv; ++r) {
     const double2* v = V + r * ldV;
     double re = 0.0, im = 0.0;
@@ -141,6 +183,7 @@ __global__ __launch_bounds__(kGsThreads) void k_scale_into(const double2* __rest
 hipError_t launch_gemv_ch(const double2* E, int64_t ldE, int64_t k, const double2* V, int64_t ldV, int64_t nv,
                           int64_t N, double2* G, hipStream_t s) {
   if (k <= 0) return hipSuccess;
+  if (nv > 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kGsThreads), 0, s, E, ldE, k, V, ldV, nv, N, G);
   return hipGetLastError();
 }
