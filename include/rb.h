@@ -450,7 +450,7 @@ int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64
  * Learned coefficient surrogate (not part of the paper's method: an MLP that
  * predicts the projection coefficients c = E^H s of a snapshot from its
  * parameters, with the plain projection of the regenerated snapshot as the
- * judge and fallback).  Network din -> hidden -> hidden -> hidden -> dout,
+ * check and fallback).  Network din -> hidden -> hidden -> hidden -> dout,
  * tanh hidden layers, linear output; BF16 weights and activations, FP32
  * accumulation on BF16 matrix cores, FP32 master weights for Adam.
  *

@@ -2,7 +2,7 @@
 for the projection coefficients c = E^H s of a snapshot on the greedy basis,
 trained on the method's own output (the projection of the training
 snapshots) with the library's BF16 matrix-core forward/backward kernels and
-Adam.  The plain projection of the regenerated snapshot judges each
+Adam.  The plain projection of the regenerated snapshot checks each
 prediction and replaces it when its relative error exceeds a threshold.
 
 Everything numeric runs in librb.so (rb_mlp_*, rb_coef_*, rb_chirp_fill,
@@ -140,7 +140,7 @@ def coef_relerr(Yh: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
 def evaluate(sur: Surrogate, E: torch.Tensor, params: torch.Tensor, N: int, flo: float, fhi: float,
              chunk: int = 16384, thresholds=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6)) -> dict:
     """Held-out evaluation: per chunk, regenerate the snapshots (FP64), project
-    them on E (the judge), predict with the surrogate, and compare.  Returns
+    them on E (the reference), predict with the surrogate, and compare.  Returns
     the error distribution, fallback rates and both throughputs."""
     M = params.shape[0]
     errs = torch.empty(M, dtype=torch.float64, device=params.device)

@@ -23,7 +23,7 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def rb():
-    """The product binding; on a GPU machine its HIP library must load."""
+    """The product binding; on a machine with a GPU its HIP library must load."""
     if not gpu_available():
         pytest.skip("no GPU")
     import paper_1805_06124_amd as rbmod
