@@ -477,7 +477,8 @@ int rb_mlp_loss(const float *Y, const float *T, int64_t batch, int dout, uint16_
 
 /* Gradients of the loss w.r.t. all parameters into grad (FP32, p32 layout),
  * given dY (BF16; NULL = the workspace's) and the activations of the last
- * forward on the same X. */
+ * forward on the same X.  Every sum over the batch is added in a fixed
+ * order, so repeated calls give identical bits. */
 int rb_mlp_backward(const float *p32, const uint16_t *p16, int din, int hidden, int dout, const float *X,
                     int64_t batch, const uint16_t *dY, float *grad, void *ws, hipStream_t stream);
 
