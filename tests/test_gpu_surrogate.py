@@ -70,6 +70,20 @@ def test_gradients_match_oracle(rb, k, B, h):
         assert np.max(np.abs(a - b)) <= 8 * 2 ** -8 * np.max(np.abs(b)) + 1e-12, name
 
 
+def test_gradients_deterministic(rb):
+    """Every batch sum is added in a fixed order (split-K partials, column
+    sums): two backward passes on the same inputs give identical bits."""
+    sur, p, X, T, (din, h, dout) = _setup(rb, k=141, B=4096)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    grads = []
+    for _ in range(2):
+        Y = sur.forward(Xd)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        sur.loss_backward(Xd, Y, Td, loss)
+        grads.append(sur.grad.clone())
+    assert torch.equal(grads[0], grads[1])
+
+
 def test_adam_matches_oracle(rb):
     sur, p, X, T, (din, h, dout) = _setup(rb)
     rng = np.random.default_rng(11)
