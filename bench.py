@@ -185,6 +185,15 @@ def timed_runs(fn, steps, warmup, log, tag):
     return runs
 
 
+def run_spread(runs):
+    """Per-run wall times of the timed runs, their median and interquartile
+    range (seconds)."""
+    import numpy as np
+    t = np.array([dt for dt, _ in runs], dtype=float)
+    q1, med, q3 = np.percentile(t, [25, 50, 75])
+    return {"run_times_s": [float(x) for x in t], "median_s": float(med), "iqr_s": float(q3 - q1)}
+
+
 def orthogonality(E):
     import torch
     k = E.shape[0]
@@ -393,6 +402,7 @@ def main():
         read_gbs = max(read_gbs, read_after)
         fp64_trace = (g["piv"].copy(), g["err"].copy())
         fp64 = dict(value=sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), time_to_tol_s=t_run,
+                    runs=run_spread(runs),
                     k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                     anchors=int(g["stats"]["anchors"]), orthogonality=orthogonality(g["E"]),
                     roofline={"kernel": "k_sweep_z", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
@@ -460,6 +470,7 @@ def main():
         log("plain streaming read of S32 after the greedy runs: %.1f GB/s" % read_after)
         read32 = max(read32, read_after)
         mixed = dict(value=sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), time_to_tol_s=t_run,
+                     runs=run_spread(runs),
                      k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                      anchors=int(g["stats"]["anchors"]), exact_anchors=int(g["stats"]["regen_anchors"]),
                      misses=int(g["stats"]["misses"]), orthogonality=orthogonality(g["E"]),
@@ -502,6 +513,7 @@ def main():
                            "(basis vectors) per second, ms_per_step is the time of one run"},
         "roofline": main_leg["roofline"],
         "breakdown_ms": main_leg["breakdown_ms"],
+        "runs": main_leg["runs"],
         "cpu_baseline": cpu,
     })
     if fp64 is not None and mixed is not None:

@@ -55,3 +55,12 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_run_spread():
+    """Median and interquartile range of the timed runs (numpy's linear
+    percentiles): for 1, 2, 3, 4 s the quartiles are 1.75 and 3.25."""
+    import bench
+    r = bench.run_spread([(t, None) for t in (4.0, 1.0, 3.0, 2.0)])
+    assert r["run_times_s"] == [4.0, 1.0, 3.0, 2.0]
+    assert r["median_s"] == 2.5 and r["iqr_s"] == 1.5
