@@ -13,11 +13,13 @@
  *    with ld = N.
  *  - Pointers documented as "device" must point to device memory of the
  *    current HIP device; "host" pointers to ordinary host memory.  All memory
- *    passed in is owned by the caller; the library never frees it.  Each
- *    call allocates the scratch it needs with hipMalloc and frees it before
+ *    passed in is owned by the caller; the library never frees it.  A call
+ *    allocates the scratch it needs with hipMalloc and frees it before
  *    returning (the large ones are stated with each entry point: the
  *    greedy's anchor_max x M coefficient panel, regeneration chunks,
- *    coefficient workspaces).
+ *    coefficient workspaces), except where the caller hands in a workspace:
+ *    the greedies take one (ws, ws_bytes; sizes from rb_greedy_z_workspace
+ *    and rb_greedy_c_workspace) and then allocate nothing.
  *  - Work is enqueued on the given stream (NULL = the default stream).
  *    Calls return after that work has completed (the greedy takes a host
  *    decision after every step), except those documented as "enqueued, not
@@ -51,9 +53,14 @@ typedef enum rb_status {
   RB_EINVAL = -1,       /* bad dimensions, pointers or options */
   RB_ENOMEM = -2,       /* device allocation failed */
   RB_EDEVICE = -3,      /* HIP runtime error or no usable device */
-  RB_ENONFINITE = -4,   /* an input (S, V) holds a NaN or Inf, or a norm
-                           overflows */
-  RB_ENOCONV = -5       /* an iterative eigen-solve did not converge */
+  RB_ENONFINITE = -4,   /* an input (S, V) holds a NaN or Inf, a norm
+                           overflows, or a re-anchored or regenerated column
+                           is not finite */
+  RB_EBREAKDOWN = -5,   /* greedy: iterated Gram-Schmidt did not settle --
+                           the last of nu_max passes still shrank ||v|| by
+                           the factor kappa (Hoffmann's criterion, Sec. 6.1.2)
+                           while ||v|| >= tol */
+  RB_ENOCONV = -6       /* an iterative eigen-solve did not converge */
 } rb_status;
 
 /* Options of the greedy; rb_default_opts() fills the defaults. */
@@ -64,8 +71,10 @@ typedef struct rb_opts {
   int32_t nu_max;   /* maximum Gram-Schmidt passes per vector.  Default 4. */
   int32_t nu_min;   /* minimum passes.  Default 1.  Each pass is one classical
                        Gram-Schmidt projection in matrix-vector form,
-                       v -= E (E^H v); after nu_max passes the vector is
-                       accepted as it is. */
+                       v -= E (E^H v).  If the last of nu_max passes still
+                       shrank ||v|| by kappa, the greedy stops with
+                       RB_EBREAKDOWN when ||v|| >= tol (a vector already
+                       below tol is accepted). */
   double theta;     /* resolution threshold of the Eq. (6.3) update: when the
                        largest estimated residual^2 falls below theta times
                        the largest residual^2 at the last re-anchoring, the
@@ -89,6 +98,14 @@ typedef struct rb_opts {
                          the same, unless the sweep's largest estimate plus
                          its rounding and perturbation bound is already
                          below tol^2; 0 = no check.  Default 2. */
+  double *step_ms;    /* host, NULL or 3 * (kmax + 1) doubles, zeroed by the
+                         caller (collect_stats = 1): for basis vector i (its
+                         position in E), device milliseconds are added of its
+                         orthogonalisation (mixed: the confirmation that
+                         chose it) at [3i], of the sweep with it at [3i+1]
+                         and of the re-anchorings that followed that sweep at
+                         [3i+2]; [3k] may receive the final confirmation
+                         that found the error below tol.  Default NULL. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */
@@ -173,7 +190,8 @@ int rb_sweep_c(const void *S32, int64_t N, int64_t M, int64_t ldS, const void *e
  *   W      device, complex128 N x M, ldW >= N: working matrix for explicit
  *          re-anchoring (the residual columns s_j - E E^H s_j are written
  *          here).  May equal S (S is then overwritten with residuals), or
- *          NULL: the library allocates it on first use and frees it.
+ *          NULL: the library allocates it on first use and frees it
+ *          (not allowed with ws).
  *   E      device, complex128 N x kmax, ldE >= N: the basis e_1..e_k (out)
  *   piv    host int64[kmax]: pivot column indices (0-based) (out)
  *   err    host double[kmax+1]: err[i] = greedy error with i vectors (out)
@@ -181,13 +199,33 @@ int rb_sweep_c(const void *S32, int64_t N, int64_t M, int64_t ldS, const void *e
  *          i.e. |R_ii| (out)
  *   nu     host int32[kmax] Gram-Schmidt passes per vector, or NULL (out)
  *   k_out  host: number of basis vectors k (out)
+ *   ws     device workspace of ws_bytes >= rb_greedy_z_workspace(N, M,
+ *          kmax, opts) bytes, 256-byte aligned, or NULL.  With ws the call
+ *          allocates nothing (no device or pinned host memory); without it
+ *          the same scratch is allocated and freed inside the call.  Its
+ *          contents on entry do not matter; calls that share one ws must not
+ *          overlap.
  *   opts   NULL = defaults;  stats: NULL or host rb_stats (out)
  * kmax is clamped to min(N, M).  If max ||s_j|| < tol, k = 0.
- * Returns RB_OK, RB_KMAX or RB_RANK on success.
+ * Returns RB_OK, RB_KMAX or RB_RANK on success; RB_ENOMEM if ws_bytes is too
+ * small (checked before any device work); RB_EBREAKDOWN (see nu_min);
+ * RB_ENONFINITE if S, a re-anchored column or a swept estimate is not finite.
+ * On an error the outputs up to the last completed step are valid and
+ * *k_out is not written.
  */
 int rb_greedy_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
                 int64_t ldW, void *E, int64_t ldE, int64_t *piv, double *err, double *rho, int32_t *nu,
-                int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+                int64_t *k_out, void *ws, size_t ws_bytes, const rb_opts *opts, rb_stats *stats,
+                hipStream_t stream);
+
+/*
+ * rb_greedy_z_workspace -- bytes of device workspace rb_greedy_z and
+ * rb_greedy_resume_z need for these sizes and options (opts NULL =
+ * defaults): per-column norms, estimates and mask (25 M bytes), the
+ * coefficient panel (16 anchor_max M bytes), argmax partials and
+ * Gram-Schmidt vectors.  0 for invalid sizes.
+ */
+size_t rb_greedy_z_workspace(int64_t N, int64_t M, int64_t kmax, const rb_opts *opts);
 
 /*
  * rb_regen_fn -- regenerates snapshot columns in FP64 from their parameters
@@ -243,13 +281,28 @@ int rb_chirp_regen(void *ctx, const int64_t *cols, int64_t n, void *out, int64_t
  *   S32    device, complex64 N x M, ldS >= N (read only unless W32 == S32)
  *   regen, regen_ctx   column regenerator (required)
  *   W32    device, complex64 N x M working matrix (ldW), may equal S32, or
- *          NULL (allocated on first use)
+ *          NULL (allocated on first use; not allowed with ws)
+ *   ws     device workspace of ws_bytes >= rb_greedy_c_workspace(N, M, kmax,
+ *          opts) bytes, or NULL (as rb_greedy_z; the regenerator is the
+ *          caller's and may allocate what it needs)
  *   E, piv, err, rho, nu, k_out, opts, stats: as rb_greedy_z (E is FP64)
+ * Returns as rb_greedy_z; RB_EBREAKDOWN when the chosen candidate's
+ * Gram-Schmidt did not settle; RB_ENONFINITE also for a non-finite
+ * regenerated candidate.
  */
 int rb_greedy_c(const void *S32, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
                 rb_regen_fn regen, void *regen_ctx, void *W32, int64_t ldW, void *E, int64_t ldE,
-                int64_t *piv, double *err, double *rho, int32_t *nu, int64_t *k_out, const rb_opts *opts,
-                rb_stats *stats, hipStream_t stream);
+                int64_t *piv, double *err, double *rho, int32_t *nu, int64_t *k_out, void *ws, size_t ws_bytes,
+                const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
+ * rb_greedy_c_workspace -- bytes of device workspace rb_greedy_c needs:
+ * that of rb_greedy_z plus the 8 candidate columns and, for the exact
+ * re-anchorings, regen_chunk FP64 columns with their min(kmax, N) x
+ * regen_chunk coefficients (16 regen_chunk (N + min(kmax, N)) bytes).
+ * 0 for invalid sizes.
+ */
+size_t rb_greedy_c_workspace(int64_t N, int64_t M, int64_t kmax, const rb_opts *opts);
 
 /*
  * rb_project_z -- C = E^H S (the coefficients of every snapshot on the
@@ -278,11 +331,13 @@ int rb_project_z(const void *E, int64_t N, int64_t k, int64_t ldE, const void *S
  *   piv, err, rho, nu  indexed by the basis position: entries k0..k-1
  *          (err: k0..k) are written, lower entries are left untouched;
  *          piv holds column indices of S
+ *   ws, ws_bytes  as rb_greedy_z (rb_greedy_z_workspace sizes it)
  * kmax is clamped to min(N, k0 + M).  Returns as rb_greedy_z.
  */
 int rb_greedy_resume_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
                        int64_t ldW, void *E, int64_t ldE, int64_t k0, int64_t *piv, double *err, double *rho,
-                       int32_t *nu, int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+                       int32_t *nu, int64_t *k_out, void *ws, size_t ws_bytes, const rb_opts *opts,
+                       rb_stats *stats, hipStream_t stream);
 
 /*
  * rb_residual_norms_z -- out-of-sample validation (Sec. 6.1): the explicit
@@ -337,7 +392,7 @@ int rb_enrich_z(rb_regen_fn regen, void *regen_ctx, int64_t N, int64_t Mv, int64
                 const rb_opts *opts, rb_stats *stats, hipStream_t stream);
 
 /*
- * rb_reconstruct_z -- the reconstruction algorithm (Alg. 4, Sec. 5.3;
+ * rb_reconstruct_z -- the reconstruction algorithm (Alg. 4, Sec. 5.2.2;
  * Theorem 5.8).  After a j-term greedy, the coefficients C = E^H S equal
  * R(1:j, :) up to the column order.  With the SVD C = V Sigma W^H, the
  * routine keeps k = #{i : sigma_i >= tau2} (so sigma_{k+1} < tau2 <= sigma_k)

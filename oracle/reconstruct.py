@@ -1,4 +1,4 @@
-"""Oracle for the reconstruction algorithm (Alg. 4, Sec. 5.3; Theorem 5.8).
+"""Oracle for the reconstruction algorithm (Alg. 4, Sec. 5.2.2; Theorem 5.8).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the product library.

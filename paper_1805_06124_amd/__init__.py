@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librb.so")
 
 STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE",
-          -5: "ENOCONV"}
+          -5: "EBREAKDOWN", -6: "ENOCONV"}
 
 
 class RBError(RuntimeError):
@@ -33,7 +33,8 @@ class RBError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("nu_max", ctypes.c_int32), ("nu_min", ctypes.c_int32),
                 ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
-                ("theta32", ctypes.c_double), ("regen_chunk", ctypes.c_int32), ("certify", ctypes.c_int32)]
+                ("theta32", ctypes.c_double), ("regen_chunk", ctypes.c_int32), ("certify", ctypes.c_int32),
+                ("step_ms", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -55,7 +56,7 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
            "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z",
-           "rb_chirp_params", "rb_stream_read"]
+           "rb_chirp_params", "rb_stream_read", "rb_greedy_z_workspace", "rb_greedy_c_workspace"]
 
 _lib = None
 
@@ -81,11 +82,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_sweep_z.restype = ctypes.c_int
     L.rb_sweep_z.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(I64), P]
     L.rb_greedy_z.restype = ctypes.c_int
-    L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
+    SZ = ctypes.c_size_t
+    L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64), P, SZ,
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_greedy_z_workspace.restype = SZ
+    L.rb_greedy_z_workspace.argtypes = [I64, I64, I64, ctypes.POINTER(Opts)]
+    L.rb_greedy_c_workspace.restype = SZ
+    L.rb_greedy_c_workspace.argtypes = [I64, I64, I64, ctypes.POINTER(Opts)]
     L.rb_greedy_resume_z.restype = ctypes.c_int
     L.rb_greedy_resume_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, I64, P, P, P, P, ctypes.POINTER(I64),
-                                     ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+                                     P, SZ, ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_residual_norms_z.restype = ctypes.c_int
     L.rb_residual_norms_z.argtypes = [P, I64, I64, I64, P, I64, I64, P, P]
     L.rb_enrich_z.restype = ctypes.c_int
@@ -104,8 +110,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_sweep_c.restype = ctypes.c_int
     L.rb_sweep_c.argtypes = [P, I64, I64, I64, P, P, P, P, P, I64, P, P, P]
     L.rb_greedy_c.restype = ctypes.c_int
-    L.rb_greedy_c.argtypes = [P, I64, I64, I64, D, I64, P, P, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
-                              ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_greedy_c.argtypes = [P, I64, I64, I64, D, I64, P, P, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64), P,
+                              SZ, ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_chirp_table.restype = ctypes.c_int
     L.rb_chirp_table.argtypes = [D, D, I64, P, P]
     L.rb_chirp_regen.restype = ctypes.c_int
@@ -176,10 +182,46 @@ def default_opts(**kw) -> Opts:
     o = Opts()
     load().rb_default_opts(ctypes.byref(o))
     for k, v in kw.items():
-        if not hasattr(o, k):
+        if not hasattr(o, k) or k == "step_ms":
             raise TypeError("unknown option %r" % k)
         setattr(o, k, v)
     return o
+
+
+def workspace_bytes(N: int, M: int, kmax: int, mixed: bool = False, **opts) -> int:
+    """Device workspace (bytes) of greedy (mixed=False) or greedy_c for these
+    sizes and options (rb_greedy_z_workspace / rb_greedy_c_workspace)."""
+    o = default_opts(**opts)
+    f = load().rb_greedy_c_workspace if mixed else load().rb_greedy_z_workspace
+    n = f(int(N), int(M), int(kmax), ctypes.byref(o))
+    if n == 0:
+        raise ValueError("invalid sizes or options")
+    return int(n)
+
+
+def workspace(N: int, M: int, kmax: int, mixed: bool = False, device="cuda", **opts) -> torch.Tensor:
+    """A uint8 device tensor sized for greedy/greedy_c (pass it as ws=)."""
+    return torch.empty(workspace_bytes(N, M, kmax, mixed, **opts), dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    if ws is None:
+        return None, 0
+    if not ws.is_cuda or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 GPU tensor")
+    return _ptr(ws), ws.numel()
+
+
+def _trace(o: Opts, kcap: int, trace: bool):
+    """Per-step timing buffer (3 doubles per basis position) hooked into the
+    options when trace is set."""
+    import numpy as np
+    if not trace:
+        return None
+    buf = np.zeros(3 * (kcap + 1), dtype=np.float64)
+    o.collect_stats = 1
+    o.step_ms = buf.ctypes.data_as(ctypes.c_void_p).value
+    return buf
 
 
 def colnorms(S: torch.Tensor, stream=None) -> torch.Tensor:
@@ -212,13 +254,17 @@ def sweep(S: torch.Tensor, e: torch.Tensor, nrm: torch.Tensor, acc: torch.Tensor
 
 
 def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None, stream=None,
-           E0: torch.Tensor | None = None, **opts) -> dict:
+           E0: torch.Tensor | None = None, ws: torch.Tensor | None = None, trace: bool = False,
+           check: bool = True, **opts) -> dict:
     """RB-greedy (Alg. 3) over complex128 S.  W: optional (M, N) working matrix
     for re-anchoring (may be S itself: S is then overwritten).  E0: optional
     (k0, N) orthonormal basis to continue from (rb_greedy_resume_z); kmax
-    then counts all vectors.  Returns dict with E (k, N) complex128 on the
-    GPU, piv, err, rho, nu (numpy; the k - k0 new steps, err from k0 to k),
-    k, k0, status and stats."""
+    then counts all vectors.  ws: optional workspace (workspace()); the call
+    then allocates nothing (W required).  trace: per-step device times
+    (step_ms, (k, 3): orthogonalisation, sweep, re-anchoring).  check=False
+    returns error statuses in the dict instead of raising.  Returns dict
+    with E (k, N) complex128 on the GPU, piv, err, rho, nu (numpy; the
+    k - k0 new steps, err from k0 to k), k, k0, status and stats."""
     import numpy as np
     M, N, ld = _mat(S, torch.complex128)
     k0 = 0
@@ -236,8 +282,9 @@ def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None
     err = np.zeros(kcap + 1, dtype=np.float64)
     rho = np.zeros(max(kcap, 1), dtype=np.float64)
     nu = np.zeros(max(kcap, 1), dtype=np.int32)
-    kout = ctypes.c_int64()
+    kout = ctypes.c_int64(k0)
     o = default_opts(**opts)
+    tr = _trace(o, kcap, trace)
     st = Stats()
     if W is not None:
         Mw, Nw, ldW = _mat(W, torch.complex128)
@@ -245,18 +292,24 @@ def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None
             raise ValueError("W must have the shape of S")
     else:
         ldW = N
+    wp, wn = _ws(ws)
     hp = [a.ctypes.data_as(ctypes.c_void_p) for a in (piv, err, rho, nu)]
+    ok = (0, 1, 2) if check else tuple(STATUS)
     if k0:
         rc = load().rb_greedy_resume_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N, k0,
-                                       *hp, ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
-        _check("rb_greedy_resume_z", rc, ok=(0, 1, 2))
+                                       *hp, ctypes.byref(kout), wp, wn, ctypes.byref(o), ctypes.byref(st),
+                                       _stream(stream))
+        _check("rb_greedy_resume_z", rc, ok=ok)
     else:
         rc = load().rb_greedy_z(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), N, *hp,
-                                ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
-        _check("rb_greedy_z", rc, ok=(0, 1, 2))
+                                ctypes.byref(kout), wp, wn, ctypes.byref(o), ctypes.byref(st), _stream(stream))
+        _check("rb_greedy_z", rc, ok=ok)
     k = kout.value
-    return dict(E=E[:k], piv=piv[k0:k].copy(), err=err[k0:k + 1].copy(), rho=rho[k0:k].copy(),
-                nu=nu[k0:k].copy(), k=k, k0=k0, status=STATUS[rc], stats=st.as_dict())
+    out = dict(E=E[:k], piv=piv[k0:k].copy(), err=err[k0:k + 1].copy(), rho=rho[k0:k].copy(),
+               nu=nu[k0:k].copy(), k=k, k0=k0, status=STATUS[rc], stats=st.as_dict())
+    if tr is not None:
+        out["step_ms"] = tr.reshape(-1, 3)[k0:k + 1].copy()
+    return out
 
 
 def residual_norms(E: torch.Tensor, V: torch.Tensor, stream=None) -> torch.Tensor:
@@ -345,11 +398,13 @@ def sweep_c(S32: torch.Tensor, e32: torch.Tensor, nrm: torch.Tensor, acc: torch.
 
 
 def greedy_c(S32: torch.Tensor, tol: float, kmax: int, params: torch.Tensor, flo: float, fhi: float,
-             W: torch.Tensor | None = None, stream=None, **opts) -> dict:
+             W: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None, trace: bool = False,
+             check: bool = True, **opts) -> dict:
     """Mixed-precision RB-greedy over complex64 S32 (basis in FP64).  Columns
     are regenerated in FP64 by the built-in chirp regenerator from `params`
     ((M, 2) float64 on the GPU: Mtot in solar masses, q) on [flo, fhi].
-    W: optional (M, N) complex64 working matrix (may be S32 itself)."""
+    W: optional (M, N) complex64 working matrix (may be S32 itself).  ws,
+    trace, check: as greedy (ws from workspace(..., mixed=True))."""
     import numpy as np
     M, N, ld = _mat(S32, torch.complex64)
     if not params.is_cuda or params.dtype != torch.float64 or params.numel() != 2 * M or not params.is_contiguous():
@@ -362,6 +417,7 @@ def greedy_c(S32: torch.Tensor, tol: float, kmax: int, params: torch.Tensor, flo
     nu = np.zeros(max(kcap, 1), dtype=np.int32)
     kout = ctypes.c_int64()
     o = default_opts(**opts)
+    tr = _trace(o, kcap, trace)
     st = Stats()
     if W is not None:
         Mw, Nw, ldW = _mat(W, torch.complex64)
@@ -377,12 +433,15 @@ def greedy_c(S32: torch.Tensor, tol: float, kmax: int, params: torch.Tensor, flo
     rc = L.rb_greedy_c(_ptr(S32), N, M, ld, float(tol), int(kmax), fn, ctypes.cast(ctypes.pointer(ctx), ctypes.c_void_p),
                        _ptr(W), ldW, _ptr(E), N, piv.ctypes.data_as(ctypes.c_void_p),
                        err.ctypes.data_as(ctypes.c_void_p), rho.ctypes.data_as(ctypes.c_void_p),
-                       nu.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st),
-                       _stream(stream))
-    _check("rb_greedy_c", rc, ok=(0, 1, 2))
+                       nu.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kout), *_ws(ws), ctypes.byref(o),
+                       ctypes.byref(st), _stream(stream))
+    _check("rb_greedy_c", rc, ok=(0, 1, 2) if check else tuple(STATUS))
     k = kout.value
-    return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
-                status=STATUS[rc], stats=st.as_dict())
+    out = dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
+               status=STATUS[rc], stats=st.as_dict())
+    if tr is not None:
+        out["step_ms"] = tr.reshape(-1, 3)[:k + 1].copy()
+    return out
 
 
 def project(E: torch.Tensor, S: torch.Tensor, stream=None) -> torch.Tensor:

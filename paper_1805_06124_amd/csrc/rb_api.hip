@@ -60,6 +60,7 @@ void rb_default_opts(rb_opts* o) {
   o->theta32 = 1e-4;
   o->regen_chunk = 32768;
   o->certify = 2;
+  o->step_ms = nullptr;
 }
 
 const char* rb_strerror(int status) {
@@ -70,7 +71,8 @@ const char* rb_strerror(int status) {
     case RB_EINVAL: return "invalid argument";
     case RB_ENOMEM: return "device allocation failed";
     case RB_EDEVICE: return "HIP runtime error";
-    case RB_ENONFINITE: return "non-finite value in S";
+    case RB_ENONFINITE: return "non-finite value (input, re-anchored column or estimate)";
+    case RB_EBREAKDOWN: return "iterated Gram-Schmidt did not settle within nu_max passes";
     case RB_ENOCONV: return "an iterative eigen-solve did not converge";
     default: return "unknown status";
   }
@@ -141,88 +143,132 @@ int rb_chirp_fill(const double* params, int64_t M, double flo, double fhi, int64
 
 namespace rb {
 
+namespace {
+
+// Device scratch of the FP64 greedy, carved from one workspace.
+struct ZScratch {
+  double *nrm, *nrm0, *acc, *sq;
+  uint8_t* mask;
+  ArgMax *part, *res;
+  double2 *cpan, *v, *g;
+  int* bad;
+  // returns the bytes used (base == nullptr: sizing only)
+  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel) {
+    Carve c(base);
+    nrm = c.take<double>(M);
+    nrm0 = c.take<double>(M);
+    acc = c.take<double>(M);
+    mask = c.take<uint8_t>(M);
+    part = c.take<ArgMax>(sweep_partials_needed(M));
+    res = c.take<ArgMax>(1);
+    cpan = c.take<double2>((size_t)panel * (size_t)M);  // panel row r (vector a + r) at r*M
+    v = c.take<double2>(N);
+    g = c.take<double2>(kcap > 0 ? kcap : 1);
+    sq = c.take<double>(4);
+    bad = c.take<int>(1);
+    return c.used;
+  }
+};
+
+bool z_opts_ok(const rb_opts& o) {
+  return o.kappa > 1.0 && o.nu_max >= 1 && o.nu_min >= 1 && o.nu_min <= o.nu_max && o.theta > 0.0 &&
+         o.theta < 1.0 && o.anchor_max >= 1;
+}
+
+}  // namespace
+
+size_t greedy_z_ws_bytes(int64_t N, int64_t M, int64_t kmax, const rb_opts* opts_in) {
+  rb_opts o;
+  rb_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (N <= 0 || M <= 0 || kmax < 0 || !z_opts_ok(o)) return 0;
+  ZScratch z;
+  return z.carve(nullptr, N, M, std::min(kmax, N), o.anchor_max);
+}
+
 // The FP64 greedy, started from k0 >= 0 orthonormal vectors already in
 // E[:, 0..k0-1] (k0 = 0: the greedy of Alg. 3 itself).
 int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
                   void* W_, int64_t ldW, void* E_, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
-                  int32_t* nu, int64_t* k_out, const rb_opts* opts_in, rb_stats* stats, hipStream_t stream) {
+                  int32_t* nu, int64_t* k_out, void* ws, size_t ws_bytes, const rb_opts* opts_in, rb_stats* stats,
+                  hipStream_t stream) {
   const auto t_begin = std::chrono::steady_clock::now();
   rb_opts o;
   rb_default_opts(&o);
   if (opts_in) o = *opts_in;
-  char msg[160];
-  auto bad = [&](const char* what) {
-    std::snprintf(msg, sizeof msg, "%s: %s", fn, what);
-    return set_error(RB_EINVAL, msg);
-  };
+  auto fail = [&](int code, const char* what) { return set_error(code, "%s: %s", fn, what); };
   if (!S_ || N <= 0 || M <= 0 || !valid_ld(N, ldS) || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol) || !piv ||
       !err || !rho || !k_out || k0 < 0)
-    return bad("bad arguments");
-  if ((kmax > 0 || k0 > 0) && (!E_ || !valid_ld(N, ldE))) return bad("bad basis buffer");
-  if (W_ && !valid_ld(N, ldW)) return bad("bad working-matrix leading dimension");
-  if (W_ == S_ && W_ && ldW != ldS) return bad("W == S needs ldW == ldS");
-  if (!(o.kappa > 1.0) || o.nu_max < 1 || o.nu_min < 1 || o.nu_min > o.nu_max || !(o.theta > 0.0) ||
-      !(o.theta < 1.0) || o.anchor_max < 1)
-    return bad("bad options");
+    return fail(RB_EINVAL, "bad arguments");
+  if ((kmax > 0 || k0 > 0) && (!E_ || !valid_ld(N, ldE))) return fail(RB_EINVAL, "bad basis buffer");
+  if (W_ && !valid_ld(N, ldW)) return fail(RB_EINVAL, "bad working-matrix leading dimension");
+  if (W_ == S_ && W_ && ldW != ldS) return fail(RB_EINVAL, "W == S needs ldW == ldS");
+  if (!z_opts_ok(o)) return fail(RB_EINVAL, "bad options");
+  if (ws && !W_) return fail(RB_EINVAL, "a caller workspace needs a working matrix W (W may be S)");
+  if (ws && reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(RB_EINVAL, "workspace not 256-byte aligned");
 
   const double2* S = static_cast<const double2*>(S_);
   double2* E = static_cast<double2*>(E_);
   int64_t kcap = kmax;
   if (kcap > N) kcap = N;
   if (kcap > k0 + M) kcap = k0 + M;
-  if (k0 > kcap) return bad("the starting basis is larger than kmax or N");
+  if (k0 > kcap) return fail(RB_EINVAL, "the starting basis is larger than kmax or N");
   const int64_t panel = o.anchor_max;
   const int64_t np = sweep_partials_needed(M);
+
+  // scratch: the caller's workspace, or one allocation of the same layout
+  ZScratch z;
+  const size_t need = z.carve(nullptr, N, M, std::min(kmax, N), panel);
+  DevBuf d_ws, d_Wown;
+  if (ws) {
+    if (ws_bytes < need) {
+      char m[160];
+      std::snprintf(m, sizeof m, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+      return fail(RB_ENOMEM, m);
+    }
+  } else {
+    RB_ALLOC(d_ws, need);
+    ws = d_ws.p;
+  }
+  z.carve(ws, N, M, std::min(kmax, N), panel);
+  HostWords hw;
+  if (hw.init(d_ws.p != nullptr, 64) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
+  ArgMax* h_res = hw.at<ArgMax>(0);     // 16 B
+  double* h_sc = hw.at<double>(16);     // scalars
+  int* h_bad = hw.at<int>(48);
 
   rb_stats st;
   std::memset(&st, 0, sizeof st);
   EventTimer tm(o.collect_stats != 0, stream);
+  double* step_ms = (tm.on && o.step_ms) ? o.step_ms : nullptr;
+  auto slot = [&](int64_t i, int part) -> double* {
+    return (step_ms && i <= kcap) ? step_ms + 3 * i + part : nullptr;
+  };
 
-  DevBuf d_nrm, d_nrm0, d_acc, d_mask, d_part, d_res, d_cpan, d_v, d_g, d_sq, d_bad, d_Wown;
-  RB_ALLOC(d_nrm, sizeof(double) * M);
-  RB_ALLOC(d_nrm0, sizeof(double) * M);
-  RB_ALLOC(d_acc, sizeof(double) * M);
-  RB_ALLOC(d_mask, M);
-  RB_ALLOC(d_part, sizeof(ArgMax) * np);
-  RB_ALLOC(d_res, sizeof(ArgMax));
-  RB_ALLOC(d_cpan, sizeof(double2) * (size_t)panel * (size_t)M);
-  RB_ALLOC(d_v, sizeof(double2) * N);
-  RB_ALLOC(d_g, sizeof(double2) * (kcap > 0 ? kcap : 1));
-  RB_ALLOC(d_sq, sizeof(double) * 4);
-  RB_ALLOC(d_bad, sizeof(int));
-  HostBuf h;
-  if (h.alloc(64) != hipSuccess) return set_error(RB_ENOMEM, "pinned host allocation failed");
-  ArgMax* h_res = h.as<ArgMax>();                          // 16 B
-  double* h_sc = reinterpret_cast<double*>(h.as<char>() + 16);  // scalars
-  int* h_bad = reinterpret_cast<int*>(h.as<char>() + 48);
-
-  double* nrm = d_nrm.as<double>();
-  double* nrm0 = d_nrm0.as<double>();
-  double* acc = d_acc.as<double>();
-  uint8_t* mask = d_mask.as<uint8_t>();
-  ArgMax* part = d_part.as<ArgMax>();
-  ArgMax* res = d_res.as<ArgMax>();
-  double2* cpan = d_cpan.as<double2>();  // panel row r (vector a + r) at cpan + r*M
-  double2* v = d_v.as<double2>();
-  double2* g = d_g.as<double2>();
-  double* sq = d_sq.as<double>();
+  double* nrm = z.nrm;
+  double* nrm0 = z.nrm0;
+  double* acc = z.acc;
+  uint8_t* mask = z.mask;
+  ArgMax* part = z.part;
+  ArgMax* res = z.res;
+  double2* cpan = z.cpan;
+  double2* v = z.v;
+  double2* g = z.g;
+  double* sq = z.sq;
 
   // ---- initial norms (Alg. 3: sigma_0(s_i) = ||s_i||) ----
   tm.start();
-  RB_HIP(hipMemsetAsync(d_bad.p, 0, sizeof(int), stream));
-  RB_HIP(launch_colnorms_z(S, N, M, ldS, nrm, d_bad.as<int>(), stream));
-  RB_HIP(hipMemcpyAsync(h_bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RB_HIP(launch_fill(z.bad, 0, 1, stream));
+  RB_HIP(launch_colnorms_z(S, N, M, ldS, nrm, z.bad, stream));
+  RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
   RB_HIP(hipMemcpyAsync(nrm0, nrm, sizeof(double) * M, hipMemcpyDeviceToDevice, stream));
-  RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
-  RB_HIP(hipMemsetAsync(mask, 0, M, stream));
+  RB_HIP(launch_fill(acc, 0.0, M, stream));
+  RB_HIP(launch_fill(mask, (uint8_t)0, M, stream));
   RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
   RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
   RB_HIP(hipStreamSynchronize(stream));
-  tm.stop(&st.ms_anchor);
-  if (*h_bad) {
-    std::snprintf(msg, sizeof msg, "%s: S holds a non-finite value", fn);
-    return set_error(RB_ENONFINITE, msg);
-  }
+  lap(tm, &st.ms_anchor, nullptr);
+  if (*h_bad) return fail(RB_ENONFINITE, "S holds a non-finite value");
 
   // working matrix X: S until the first anchoring, W afterwards
   const double2* X = S;
@@ -236,6 +282,15 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   int64_t a = 0;          // first basis vector in the coefficient panel
   int64_t m = 0;          // vectors swept since the last anchoring
   int status = RB_KMAX;
+  // an error found after the run started: the outputs of the k completed
+  // vectors stay valid
+  auto fail_run = [&](int code, const char* what) {
+    char m2[200];
+    std::snprintf(m2, sizeof m2, "%s (after %lld basis vectors)", what, (long long)k);
+    *k_out = k;
+    if (stats) *stats = st;
+    return fail(code, m2);
+  };
 
   // ---- continuation: reduce every column against the k0 given vectors ----
   // X <- S - E0 (E0^H S), a block at a time (at most `panel` vectors per
@@ -251,19 +306,21 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     for (int64_t b0 = 0; b0 < k0; b0 += panel) {
       const int64_t pb = std::min<int64_t>(panel, k0 - b0);
       RB_HIP(launch_project_z(E + b0 * ldE, N, pb, ldE, X, M, ldX, cpan, pb, stream));
-      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + b0 * ldE, ldE, pb, cpan, 1, pb, nrm, d_bad.as<int>(), stream));
+      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + b0 * ldE, ldE, pb, cpan, 1, pb, nrm, z.bad, stream));
       X = W;
       ldX = ldWk;
     }
     written = true;
     RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    tm.stop(&st.ms_anchor);
+    lap(tm, &st.ms_anchor, nullptr);
     st.anchors++;
+    k = a = k0;
+    if (*h_bad) return fail_run(RB_ENONFINITE, "a reduced column is not finite");
     A_w = h_res->v;
     J = h_res->i;
-    k = a = k0;
   }
   err[k] = std::sqrt(A_w > 0.0 ? A_w : 0.0);
 
@@ -275,7 +332,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   // in err that stays far below the rounding of the explicit form).
   // Either way acc <- 0 and the pivot is the argmax of the fresh norms.
   double A_X = A_w;  // largest nrm of X when it was last written
-  auto anchor = [&](bool write) -> int {
+  auto anchor = [&](bool write, double* slot_ms) -> int {
     tm.start();
     if (write && !W) {
       const size_t bytes = sizeof(double2) * (size_t)N * (size_t)M;
@@ -284,34 +341,36 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
       ldWk = N;
     }
     if (write) {
-      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(), stream));
+      RB_HIP(launch_resid(X, ldX, W, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, z.bad, stream));
       X = W;
       ldX = ldWk;
       written = true;
     } else {
       RB_HIP(launch_resid(X, ldX, static_cast<double2*>(nullptr), 0, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm,
-                          d_bad.as<int>(), stream));
+                          z.bad, stream));
     }
-    RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
+    RB_HIP(launch_fill(acc, 0.0, M, stream));
     RB_HIP(launch_est_argmax(nrm, nullptr, mask, M, part, np, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    tm.stop(&st.ms_anchor);
+    lap(tm, &st.ms_anchor, slot_ms);
+    st.anchors++;
+    if (*h_bad) return fail_run(RB_ENONFINITE, "a re-anchored column is not finite");
     if (write) {
       a = k;
       m = 0;
       A_X = h_res->v;
     }
     A_w = h_res->v;
-    st.anchors++;
     return RB_OK;
   };
   // a norms-only anchoring keeps the extra estimate error 2 m u sqrt(A_X)
   // rho below a tenth of the resolution threshold theta rho^2
   auto norms_only_ok = [&](double est) -> bool {
     if (!written) return false;
-    const double rho = std::sqrt(est > 0.0 ? est : 0.0);
-    return 2.0 * (double)panel * 0x1p-53 * std::sqrt(A_X) <= 0.1 * o.theta * rho;
+    const double r = std::sqrt(est > 0.0 ? est : 0.0);
+    return 2.0 * (double)panel * 0x1p-53 * std::sqrt(A_X) <= 0.1 * o.theta * r;
   };
 
   while (true) {
@@ -340,9 +399,11 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     double after = before;
     const double* scale_src = nrm + J;  // k == 0: the exact column norm
     int passes = 0;
+    bool settled = true;  // the last pass met Hoffmann's criterion
     if (k == 0) {
       passes = 1;  // a pass against an empty basis changes nothing
     } else {
+      settled = false;
       while (passes < o.nu_max) {
         RB_HIP(launch_gemv_ch(E, ldE, k, v, N, 1, N, g, stream));
         RB_HIP(launch_gemv_n_sub(E, ldE, k, g, v, N, 1, N, stream));
@@ -351,21 +412,32 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
         RB_HIP(hipStreamSynchronize(stream));
         ++passes;
         after = std::sqrt(h_sc[2]);
-        if (passes >= o.nu_min && after > before / o.kappa) break;
+        if (passes >= o.nu_min && after > before / o.kappa) {
+          settled = true;
+          break;
+        }
         before = after;
       }
       scale_src = sq;
     }
     st.gs_passes += passes;
     const double r = after;
+    lap(tm, &st.ms_gs, slot(k, 0));
+    if (!std::isfinite(r)) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
     if (!(r > 64.0 * 0x1p-53 * s_norm)) {  // numerically in span(E)
-      tm.stop(&st.ms_gs);
       status = RB_RANK;
       break;
     }
+    if (!settled && r >= tol) {
+      char m2[160];
+      std::snprintf(m2, sizeof m2, "Gram-Schmidt of pivot %lld still shrank ||v|| by kappa after %d passes",
+                    (long long)J, passes);
+      return fail_run(RB_EBREAKDOWN, m2);
+    }
+    tm.start();
     RB_HIP(launch_scale_into(v, N, scale_src, E + k * ldE, stream));
-    RB_HIP(hipMemsetAsync(mask + J, 1, 1, stream));
-    tm.stop(&st.ms_gs);
+    RB_HIP(launch_fill(mask + J, (uint8_t)1, 1, stream));
+    lap(tm, &st.ms_gs, slot(k, 0));
     piv[k] = J;
     rho[k] = r;
     if (nu) nu[k] = passes;
@@ -373,7 +445,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
 
     // ---- 2. fused sweep with the new vector (panel row m) ----
     if (m == panel) {
-      int rc = anchor(true);
+      int rc = anchor(true, slot(k - 1, 2));
       if (rc != RB_OK) return rc;
       // the new vector has not been swept yet: the panel restarts at it
       a = k - 1;
@@ -381,7 +453,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     tm.start();
     RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr,
                           stream));
-    tm.stop(&st.ms_sweep);  // the sweep kernel alone
+    lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
     RB_HIP(launch_sweep_final(M, part, res, stream));
     RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
@@ -389,10 +461,11 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     ++m;
     double est_max = h_res->v;
     J = h_res->i;
+    if (J >= 0 && std::isnan(est_max)) return fail_run(RB_ENONFINITE, "a swept estimate is not finite");
 
     // ---- 3. resolution check and error ----
     if (J >= 0 && est_max < o.theta * A_w) {
-      int rc = anchor(!norms_only_ok(est_max));
+      int rc = anchor(!norms_only_ok(est_max), slot(k - 1, 2));
       if (rc != RB_OK) return rc;
       est_max = h_res->v;
       J = h_res->i;
@@ -411,19 +484,24 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
 extern "C" {
 
 int rb_greedy_z(const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W, int64_t ldW,
-                void* E, int64_t ldE, int64_t* piv, double* err, double* rho, int32_t* nu, int64_t* k_out,
-                const rb_opts* opts, rb_stats* stats, hipStream_t stream) {
+                void* E, int64_t ldE, int64_t* piv, double* err, double* rho, int32_t* nu, int64_t* k_out, void* ws,
+                size_t ws_bytes, const rb_opts* opts, rb_stats* stats, hipStream_t stream) {
   last_error().clear();
-  return greedy_z_core("rb_greedy_z", S, N, M, ldS, tol, kmax, W, ldW, E, ldE, 0, piv, err, rho, nu, k_out, opts,
-                       stats, stream);
+  return greedy_z_core("rb_greedy_z", S, N, M, ldS, tol, kmax, W, ldW, E, ldE, 0, piv, err, rho, nu, k_out, ws,
+                       ws_bytes, opts, stats, stream);
+}
+
+size_t rb_greedy_z_workspace(int64_t N, int64_t M, int64_t kmax, const rb_opts* opts) {
+  return greedy_z_ws_bytes(N, M, kmax, opts);
 }
 
 int rb_greedy_resume_z(const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void* W,
                        int64_t ldW, void* E, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
-                       int32_t* nu, int64_t* k_out, const rb_opts* opts, rb_stats* stats, hipStream_t stream) {
+                       int32_t* nu, int64_t* k_out, void* ws, size_t ws_bytes, const rb_opts* opts, rb_stats* stats,
+                       hipStream_t stream) {
   last_error().clear();
   return greedy_z_core("rb_greedy_resume_z", S, N, M, ldS, tol, kmax, W, ldW, E, ldE, k0, piv, err, rho, nu, k_out,
-                       opts, stats, stream);
+                       ws, ws_bytes, opts, stats, stream);
 }
 
 }  // extern "C"

@@ -19,7 +19,10 @@ int set_error(int code, const char* fmt, ...);
 // point in error messages.
 int greedy_z_core(const char* fn, const void* S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax,
                   void* W, int64_t ldW, void* E, int64_t ldE, int64_t k0, int64_t* piv, double* err, double* rho,
-                  int32_t* nu, int64_t* k_out, const rb_opts* opts, rb_stats* stats, hipStream_t stream);
+                  int32_t* nu, int64_t* k_out, void* ws, size_t ws_bytes, const rb_opts* opts, rb_stats* stats,
+                  hipStream_t stream);
+// Workspace bytes of greedy_z_core (0 for invalid sizes or options).
+size_t greedy_z_ws_bytes(int64_t N, int64_t M, int64_t kmax, const rb_opts* opts);
 
 #define RB_HIP(expr)                                                                                \
   do {                                                                                              \
@@ -96,5 +99,50 @@ struct EventTimer {
 };
 
 inline bool valid_ld(int64_t N, int64_t ld) { return ld >= N && ld > 0; }
+
+// Slices of one workspace buffer, each 256-byte aligned.  With base ==
+// nullptr only the size is counted (the same sequence of take() calls sizes
+// a workspace and then carves it).
+struct Carve {
+  char* base = nullptr;
+  size_t used = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    const size_t off = (used + 255) & ~static_cast<size_t>(255);
+    used = off + sizeof(T) * (count ? count : 1);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+// Host words the greedies read back after each step: pinned memory when the
+// call may allocate, else a buffer on the caller's stack (a synchronous copy
+// to pageable memory; no allocation).
+struct HostWords {
+  HostBuf pinned;
+  alignas(64) unsigned char local[512];
+  unsigned char* p = local;
+  // bytes <= sizeof local
+  hipError_t init(bool may_alloc, size_t bytes) {
+    if (!may_alloc) return hipSuccess;
+    hipError_t e = pinned.alloc(bytes);
+    if (e == hipSuccess) p = pinned.as<unsigned char>();
+    return e;
+  }
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(p + off);
+  }
+};
+
+// Per-step and total device time of one phase (collect_stats): adds the
+// timer's interval to *total and, if slot is non-null, to *slot.
+inline void lap(EventTimer& tm, double* total, double* slot) {
+  if (!tm.on) return;
+  double t = 0.0;
+  tm.stop(&t);
+  *total += t;
+  if (slot) *slot += t;
+}
 
 }  // namespace rb

@@ -74,9 +74,11 @@ __device__ __forceinline__ dd wave_dd_sum(dd x) {
   return x;
 }
 
-// (value, index) argmax with ties to the lowest index.  The combination is
-// associative and commutative, so every reduction order gives the same
-// result.
+// (value, index) argmax with ties to the lowest index.  A NaN value ranks
+// above every number (so a non-finite estimate reaches the host instead of
+// dropping out of the search).  The combination is a maximum under a total
+// order, hence associative and commutative: every reduction order gives the
+// same result.
 struct vi {
   double v;
   int64_t i;
@@ -85,8 +87,12 @@ struct vi {
 __device__ __forceinline__ vi vi_max(vi a, vi b) {
   if (a.i < 0) return b;
   if (b.i < 0) return a;
-  if (b.v > a.v) return b;
-  if (b.v < a.v) return a;
+  const bool an = a.v != a.v, bn = b.v != b.v;
+  if (an != bn) return an ? a : b;
+  if (!an) {
+    if (b.v > a.v) return b;
+    if (b.v < a.v) return a;
+  }
   return (b.i < a.i) ? b : a;
 }
 __device__ __forceinline__ vi wave_vi_max(vi x) {
@@ -139,6 +145,11 @@ hipError_t launch_round32(const double2* x, int64_t N, float2* y, hipStream_t s)
 hipError_t launch_iota(int64_t* cols, int64_t start, int64_t n, hipStream_t s);
 // x[i] <- sqrt(x[i]), i < n
 hipError_t launch_sqrt_inplace(double* x, int64_t n, hipStream_t s);
+// p[i] <- v for i < n (a kernel, so that no memset node enters a captured
+// stream)
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill(int* p, int v, int64_t n, hipStream_t s);
 
 // Gram-Schmidt building blocks over the basis E (N x k, ldE) and nv vectors
 // V (N x nv, ldV):  G = E^H V ;  V -= E G ;  norms.

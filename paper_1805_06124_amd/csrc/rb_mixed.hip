@@ -22,6 +22,7 @@
 // A deflation is used while the accumulated perturbation stays below
 // tol / 10, or while sigma is so large that a later anchoring must still
 // come before the error can reach tol; otherwise the anchoring is exact.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -85,24 +86,95 @@ int rb_sweep_c(const void* S32, int64_t N, int64_t M, int64_t ldS, const void* e
   return RB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of the mixed greedy, carved from one workspace: the part
+// every run uses, and the exact re-anchoring's regeneration chunk.
+struct CScratch {
+  double *nrm, *acc, *sq;
+  uint8_t* mask;
+  ArgMax *part, *top;
+  double2 *cpan, *V, *G;
+  int64_t* cols;
+  float2* e32;
+  int* bad;
+  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel) {
+    Carve c(base);
+    nrm = c.take<double>(M);
+    acc = c.take<double>(M);
+    mask = c.take<uint8_t>(M);
+    part = c.take<ArgMax>(sweep32_partials_needed(M));
+    top = c.take<ArgMax>(kTop);
+    cpan = c.take<double2>((size_t)panel * (size_t)M);
+    V = c.take<double2>((size_t)N * kTop);
+    G = c.take<double2>((size_t)(kcap > 0 ? kcap : 1) * kTop);
+    sq = c.take<double>(2 * kTop);
+    cols = c.take<int64_t>(kTop);
+    e32 = c.take<float2>(N);
+    bad = c.take<int>(1);
+    return c.used;
+  }
+};
+struct CRegen {
+  double2 *S64c, *Cc;
+  int64_t* iota;
+  size_t carve(void* base, int64_t N, int64_t kcap, int64_t chunk) {
+    Carve c(base);
+    S64c = c.take<double2>((size_t)N * (size_t)chunk);
+    Cc = c.take<double2>((size_t)(kcap > 0 ? kcap : 1) * (size_t)chunk);
+    iota = c.take<int64_t>(chunk);
+    return c.used;
+  }
+};
+
+bool c_opts_ok(const rb_opts& o) {
+  return o.kappa > 1.0 && o.nu_max >= 1 && o.nu_min >= 1 && o.nu_min <= o.nu_max && o.theta32 > 0.0 &&
+         o.theta32 < 1.0 && o.anchor_max >= 1 && o.regen_chunk >= 1;
+}
+
+// both parts, 256-byte aligned one after the other
+size_t c_ws_bytes(int64_t N, int64_t M, int64_t kcap, const rb_opts& o, size_t* base_bytes) {
+  CScratch c;
+  CRegen r;
+  const int64_t chunk = o.regen_chunk < M ? o.regen_chunk : M;
+  const size_t b = (c.carve(nullptr, N, M, kcap, o.anchor_max) + 255) & ~static_cast<size_t>(255);
+  if (base_bytes) *base_bytes = b;
+  return b + r.carve(nullptr, N, kcap, chunk);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rb_greedy_c_workspace(int64_t N, int64_t M, int64_t kmax, const rb_opts* opts_in) {
+  rb_opts o;
+  rb_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (N <= 0 || M <= 0 || kmax < 0 || !c_opts_ok(o)) return 0;
+  return c_ws_bytes(N, M, std::min(std::min(kmax, N), M), o, nullptr);
+}
+
 int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, rb_regen_fn regen,
                 void* regen_ctx, void* W32_, int64_t ldW, void* E_, int64_t ldE, int64_t* piv, double* err,
-                double* rho, int32_t* nu, int64_t* k_out, const rb_opts* opts_in, rb_stats* stats,
-                hipStream_t stream) {
+                double* rho, int32_t* nu, int64_t* k_out, void* ws, size_t ws_bytes, const rb_opts* opts_in,
+                rb_stats* stats, hipStream_t stream) {
   last_error().clear();
   const auto t_begin = std::chrono::steady_clock::now();
   rb_opts o;
   rb_default_opts(&o);
   if (opts_in) o = *opts_in;
+  auto fail = [&](int code, const char* what) { return set_error(code, "rb_greedy_c: %s", what); };
   if (!S32_ || N <= 0 || M <= 0 || !valid_ld(N, ldS) || kmax < 0 || !(tol >= 0.0) || !std::isfinite(tol) ||
       !piv || !err || !rho || !k_out || !regen)
-    return set_error(RB_EINVAL, "rb_greedy_c: bad arguments");
-  if (kmax > 0 && (!E_ || !valid_ld(N, ldE))) return set_error(RB_EINVAL, "rb_greedy_c: bad basis buffer");
-  if (W32_ && !valid_ld(N, ldW)) return set_error(RB_EINVAL, "rb_greedy_c: bad working-matrix leading dimension");
-  if (W32_ == S32_ && W32_ && ldW != ldS) return set_error(RB_EINVAL, "rb_greedy_c: W32 == S32 needs ldW == ldS");
-  if (!(o.kappa > 1.0) || o.nu_max < 1 || o.nu_min < 1 || o.nu_min > o.nu_max || !(o.theta32 > 0.0) ||
-      !(o.theta32 < 1.0) || o.anchor_max < 1 || o.regen_chunk < 1)
-    return set_error(RB_EINVAL, "rb_greedy_c: bad options");
+    return fail(RB_EINVAL, "bad arguments");
+  if (kmax > 0 && (!E_ || !valid_ld(N, ldE))) return fail(RB_EINVAL, "bad basis buffer");
+  if (W32_ && !valid_ld(N, ldW)) return fail(RB_EINVAL, "bad working-matrix leading dimension");
+  if (W32_ == S32_ && W32_ && ldW != ldS) return fail(RB_EINVAL, "W32 == S32 needs ldW == ldS");
+  if (!c_opts_ok(o)) return fail(RB_EINVAL, "bad options");
+  if (ws && !W32_) return fail(RB_EINVAL, "a caller workspace needs a working matrix W32 (W32 may be S32)");
+  if (ws && reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(RB_EINVAL, "workspace not 256-byte aligned");
 
   const float2* S32 = static_cast<const float2*>(S32_);
   double2* E = static_cast<double2*>(E_);
@@ -113,43 +185,52 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
   const int64_t np = sweep32_partials_needed(M);
   const int64_t chunk = o.regen_chunk < M ? o.regen_chunk : M;
 
-  rb_stats st;
-  std::memset(&st, 0, sizeof st);
-  EventTimer tm(o.collect_stats != 0, stream);
-
-  DevBuf d_nrm, d_acc, d_mask, d_part, d_top, d_cpan, d_V, d_G, d_sq, d_cols, d_e32, d_bad;
-  DevBuf d_Wown, d_S64c, d_Cc, d_iota;
-  RB_ALLOC(d_nrm, sizeof(double) * M);
-  RB_ALLOC(d_acc, sizeof(double) * M);
-  RB_ALLOC(d_mask, M);
-  RB_ALLOC(d_part, sizeof(ArgMax) * np);
-  RB_ALLOC(d_top, sizeof(ArgMax) * kTop);
-  RB_ALLOC(d_cpan, sizeof(double2) * (size_t)panel * (size_t)M);
-  RB_ALLOC(d_V, sizeof(double2) * (size_t)N * kTop);
-  RB_ALLOC(d_G, sizeof(double2) * (size_t)(kcap > 0 ? kcap : 1) * kTop);
-  RB_ALLOC(d_sq, sizeof(double) * 2 * kTop);
-  RB_ALLOC(d_cols, sizeof(int64_t) * kTop);
-  RB_ALLOC(d_e32, sizeof(float2) * N);
-  RB_ALLOC(d_bad, sizeof(int));
-  HostBuf h;
+  // scratch: the caller's workspace (both parts), or an allocation of the
+  // base part now and of the regeneration part at the first exact anchoring
+  CScratch z;
+  CRegen rg = {nullptr, nullptr, nullptr};
+  size_t base_bytes = 0;
+  const size_t need = c_ws_bytes(N, M, kcap, o, &base_bytes);
+  DevBuf d_ws, d_regen, d_Wown;
+  if (ws) {
+    if (ws_bytes < need) {
+      char m[160];
+      std::snprintf(m, sizeof m, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+      return fail(RB_ENOMEM, m);
+    }
+    z.carve(ws, N, M, kcap, panel);
+    rg.carve(static_cast<char*>(ws) + base_bytes, N, kcap, chunk);
+  } else {
+    RB_ALLOC(d_ws, base_bytes);
+    z.carve(d_ws.p, N, M, kcap, panel);
+  }
+  HostWords hw;
   const size_t h_bytes = sizeof(ArgMax) * kTop + sizeof(double) * 2 * kTop + sizeof(int64_t) * kTop + 64;
-  if (h.alloc(h_bytes) != hipSuccess) return set_error(RB_ENOMEM, "pinned host allocation failed");
-  ArgMax* h_top = h.as<ArgMax>();
+  if (hw.init(d_ws.p != nullptr, h_bytes) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
+  ArgMax* h_top = hw.at<ArgMax>(0);
   double* h_sq = reinterpret_cast<double*>(h_top + kTop);
   int64_t* h_cols = reinterpret_cast<int64_t*>(h_sq + 2 * kTop);
   int* h_bad = reinterpret_cast<int*>(h_cols + kTop);
 
-  double* nrm = d_nrm.as<double>();
-  double* acc = d_acc.as<double>();
-  uint8_t* mask = d_mask.as<uint8_t>();
-  ArgMax* part = d_part.as<ArgMax>();
-  ArgMax* top = d_top.as<ArgMax>();
-  double2* cpan = d_cpan.as<double2>();
-  double2* V = d_V.as<double2>();
-  double2* G = d_G.as<double2>();
-  double* sq = d_sq.as<double>();
-  int64_t* cols = d_cols.as<int64_t>();
-  float2* e32 = d_e32.as<float2>();
+  rb_stats st;
+  std::memset(&st, 0, sizeof st);
+  EventTimer tm(o.collect_stats != 0, stream);
+  double* step_ms = (tm.on && o.step_ms) ? o.step_ms : nullptr;
+  auto slot = [&](int64_t i, int part) -> double* {
+    return (step_ms && i <= kcap) ? step_ms + 3 * i + part : nullptr;
+  };
+
+  double* nrm = z.nrm;
+  double* acc = z.acc;
+  uint8_t* mask = z.mask;
+  ArgMax* part = z.part;
+  ArgMax* top = z.top;
+  double2* cpan = z.cpan;
+  double2* V = z.V;
+  double2* G = z.G;
+  double* sq = z.sq;
+  int64_t* cols = z.cols;
+  float2* e32 = z.e32;
 
   const float2* X32 = S32;  // working matrix: S32 until the first anchoring
   int64_t ldX = ldS;
@@ -158,29 +239,37 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
 
   // ---- initial norms and candidates ----
   tm.start();
-  RB_HIP(hipMemsetAsync(d_bad.p, 0, sizeof(int), stream));
-  RB_HIP(launch_colnorms_c(S32, N, M, ldS, nrm, d_bad.as<int>(), stream));
-  RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
-  RB_HIP(hipMemsetAsync(mask, 0, M, stream));
+  RB_HIP(launch_fill(z.bad, 0, 1, stream));
+  RB_HIP(launch_colnorms_c(S32, N, M, ldS, nrm, z.bad, stream));
+  RB_HIP(launch_fill(acc, 0.0, M, stream));
+  RB_HIP(launch_fill(mask, (uint8_t)0, M, stream));
   RB_HIP(launch_est_topk(nrm, nullptr, mask, M, part, np, top, stream));
-  RB_HIP(hipMemcpyAsync(h_bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
   RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
   RB_HIP(hipStreamSynchronize(stream));
-  tm.stop(&st.ms_anchor);
-  if (*h_bad) return set_error(RB_ENONFINITE, "rb_greedy_c: S holds a non-finite value");
+  lap(tm, &st.ms_anchor, nullptr);
+  if (*h_bad) return fail(RB_ENONFINITE, "S holds a non-finite value");
   double A_w = h_top[0].v > 0.0 ? h_top[0].v : 0.0;
   double P = 0.5 * kDelta32 * std::sqrt(A_w);  // perturbation bound of the stored columns
 
   int64_t k = 0, a = 0, m = 0;
   int status = RB_KMAX;
+  auto fail_run = [&](int code, const char* what) {
+    char m2[200];
+    std::snprintf(m2, sizeof m2, "%s (after %lld basis vectors)", what, (long long)k);
+    *k_out = k;
+    if (stats) *stats = st;
+    return fail(code, m2);
+  };
 
   // ---- confirmation of the candidates in h_top against E[:, 0:k] ----
   int64_t Jbest = -1;
   double rbest = 0.0;
-  int slot = 0, passes = 0;
-  bool rank_flag = false;
+  int slot_b = 0, passes = 0;
+  bool rank_flag = false, settled_b = true;
   const double* sq_final = sq;
-  auto confirm = [&](int64_t kcur) -> int {
+  // slot_ms: where the confirmation's time goes (the vector it chooses)
+  auto confirm = [&](int64_t kcur, double* slot_ms) -> int {
     tm.start();
     int nv = 0;
     for (int r = 0; r < kTop; ++r)
@@ -188,18 +277,23 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     Jbest = -1;
     rbest = 0.0;
     rank_flag = false;
+    settled_b = true;
     if (nv == 0) {
-      tm.stop(&st.ms_gs);
+      lap(tm, &st.ms_gs, slot_ms);
       return RB_OK;
     }
     RB_HIP(hipMemcpyAsync(cols, h_cols, sizeof(int64_t) * nv, hipMemcpyHostToDevice, stream));
-    if (regen(regen_ctx, cols, nv, V, N, stream) != 0)
-      return set_error(RB_EDEVICE, "rb_greedy_c: regeneration callback failed");
+    if (regen(regen_ctx, cols, nv, V, N, stream) != 0) return fail_run(RB_EDEVICE, "regeneration callback failed");
     RB_HIP(launch_sqnorms_small(V, N, nv, N, sq, stream));
     RB_HIP(hipMemcpyAsync(h_sq, sq, sizeof(double) * nv, hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
     double orig[kTop], before[kTop], after[kTop];
-    for (int r = 0; r < nv; ++r) orig[r] = before[r] = after[r] = std::sqrt(h_sq[r]);
+    bool settled[kTop];
+    for (int r = 0; r < nv; ++r) {
+      orig[r] = before[r] = after[r] = std::sqrt(h_sq[r]);
+      settled[r] = true;
+      if (!std::isfinite(orig[r])) return fail_run(RB_ENONFINITE, "a regenerated candidate is not finite");
+    }
     sq_final = sq;
     passes = 1;
     if (kcur > 0) {
@@ -214,7 +308,8 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
         bool all_ok = true;
         for (int r = 0; r < nv; ++r) {
           after[r] = std::sqrt(h_sq[kTop + r]);
-          if (!(after[r] > before[r] / o.kappa)) all_ok = false;
+          settled[r] = after[r] > before[r] / o.kappa;
+          if (!settled[r]) all_ok = false;
         }
         if (passes >= o.nu_min && all_ok) break;
         for (int r = 0; r < nv; ++r) before[r] = after[r];
@@ -222,14 +317,17 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       sq_final = sq + kTop;
     }
     st.gs_passes += passes;
+    for (int r = 0; r < nv; ++r)
+      if (!std::isfinite(after[r])) return fail_run(RB_ENONFINITE, "an orthogonalised candidate is not finite");
     int b = 0;
     for (int r = 1; r < nv; ++r)
       if (after[r] > after[b] || (after[r] == after[b] && h_cols[r] < h_cols[b])) b = r;
-    slot = b;
+    slot_b = b;
     Jbest = h_cols[b];
     rbest = after[b];
+    settled_b = settled[b];
     rank_flag = !(rbest > 64.0 * 0x1p-53 * orig[b]);
-    tm.stop(&st.ms_gs);
+    lap(tm, &st.ms_gs, slot_ms);
     return RB_OK;
   };
 
@@ -242,46 +340,44 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     }
     return RB_OK;
   };
-  auto anchor = [&](bool exact) -> int {
+  auto anchor = [&](bool exact, double* slot_ms) -> int {
     tm.start();
     int rc = ensure_w();
     if (rc != RB_OK) return rc;
     if (exact) {
-      if (!d_S64c.p) {
-        RB_ALLOC(d_S64c, sizeof(double2) * (size_t)N * (size_t)chunk);
-        RB_ALLOC(d_Cc, sizeof(double2) * (size_t)(kcap > 0 ? kcap : 1) * (size_t)chunk);
-        RB_ALLOC(d_iota, sizeof(int64_t) * (size_t)chunk);
+      if (!rg.S64c) {
+        const size_t rb = rg.carve(nullptr, N, kcap, chunk);
+        RB_ALLOC(d_regen, rb);
+        rg.carve(d_regen.p, N, kcap, chunk);
       }
-      double2* S64c = d_S64c.as<double2>();
-      double2* Cc = d_Cc.as<double2>();
-      int64_t* iota = d_iota.as<int64_t>();
       for (int64_t c0 = 0; c0 < M; c0 += chunk) {
         const int64_t mc = (M - c0 < chunk) ? M - c0 : chunk;
-        RB_HIP(launch_iota(iota, c0, mc, stream));
-        if (regen(regen_ctx, iota, mc, S64c, N, stream) != 0)
-          return set_error(RB_EDEVICE, "rb_greedy_c: regeneration callback failed");
-        if (k > 0) RB_HIP(launch_project_z(E, N, k, ldE, S64c, mc, N, Cc, k, stream));
-        RB_HIP(launch_resid(S64c, N, W32 + c0 * ldWk, ldWk, N, mc, E, ldE, k, Cc, 1, k, nrm + c0,
-                            d_bad.as<int>(), stream));
+        RB_HIP(launch_iota(rg.iota, c0, mc, stream));
+        if (regen(regen_ctx, rg.iota, mc, rg.S64c, N, stream) != 0)
+          return fail_run(RB_EDEVICE, "regeneration callback failed");
+        if (k > 0) RB_HIP(launch_project_z(E, N, k, ldE, rg.S64c, mc, N, rg.Cc, k, stream));
+        RB_HIP(launch_resid(rg.S64c, N, W32 + c0 * ldWk, ldWk, N, mc, E, ldE, k, rg.Cc, 1, k, nrm + c0, z.bad,
+                            stream));
       }
       st.regen_anchors++;
     } else {
-      RB_HIP(launch_resid(X32, ldX, W32, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, d_bad.as<int>(),
-                          stream));
+      RB_HIP(launch_resid(X32, ldX, W32, ldWk, N, M, E + a * ldE, ldE, m, cpan, M, 1, nrm, z.bad, stream));
     }
     X32 = W32;
     ldX = ldWk;
-    RB_HIP(hipMemsetAsync(acc, 0, sizeof(double) * M, stream));
+    RB_HIP(launch_fill(acc, 0.0, M, stream));
     RB_HIP(launch_est_topk(nrm, nullptr, mask, M, part, np, top, stream));
     RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    tm.stop(&st.ms_anchor);
+    lap(tm, &st.ms_anchor, slot_ms);
+    st.anchors++;
+    if (*h_bad) return fail_run(RB_ENONFINITE, "a re-anchored column is not finite");
     a = k;
     m = 0;
     A_w = h_top[0].v > 0.0 ? h_top[0].v : 0.0;
     const double sig = std::sqrt(A_w);
     P = exact ? 0.5 * kDelta32 * sig : P + kDelta32 * sig;
-    st.anchors++;
     return RB_OK;
   };
   auto choose_exact = [&](double sigma) -> bool {
@@ -290,8 +386,19 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     if (kDelta32 * sigma > budget) return false;       // a later anchoring comes before tol
     return true;
   };
+  // the confirmed candidate's Gram-Schmidt must have settled unless its
+  // residual is already below tol
+  auto check_breakdown = [&]() -> int {
+    if (Jbest >= 0 && !rank_flag && !settled_b && rbest >= tol) {
+      char m2[160];
+      std::snprintf(m2, sizeof m2, "Gram-Schmidt of candidate %lld still shrank ||v|| by kappa after %d passes",
+                    (long long)Jbest, passes);
+      return fail_run(RB_EBREAKDOWN, m2);
+    }
+    return RB_OK;
+  };
 
-  int rc = confirm(0);
+  int rc = confirm(0, slot(0, 0));
   if (rc != RB_OK) return rc;
   err[0] = (Jbest >= 0) ? rbest : 0.0;
   bool certified = false;
@@ -313,10 +420,10 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       const bool bounded_ok = o.certify == 2 && h_top[0].i >= 0 &&
                               h_top[0].v + est_bound(h_top[0].v) < tol * tol;
       if (o.certify && !certified && !bounded_ok && k < kcap && Jbest >= 0) {
-        rc = anchor(true);
+        rc = anchor(true, slot(k > 0 ? k - 1 : 0, 2));
         if (rc != RB_OK) return rc;
         certified = true;
-        rc = confirm(k);
+        rc = confirm(k, slot(k, 0));
         if (rc != RB_OK) return rc;
         err[k] = (Jbest >= 0) ? rbest : 0.0;
         continue;
@@ -329,12 +436,14 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       status = RB_RANK;
       break;
     }
+    rc = check_breakdown();
+    if (rc != RB_OK) return rc;
     // ---- 1. the confirmed candidate becomes e_k ----
     tm.start();
-    RB_HIP(launch_scale_into(V + slot * N, N, sq_final + slot, E + k * ldE, stream));
+    RB_HIP(launch_scale_into(V + slot_b * N, N, sq_final + slot_b, E + k * ldE, stream));
     RB_HIP(launch_round32(E + k * ldE, N, e32, stream));
-    RB_HIP(hipMemsetAsync(mask + Jbest, 1, 1, stream));
-    tm.stop(&st.ms_gs);
+    RB_HIP(launch_fill(mask + Jbest, (uint8_t)1, 1, stream));
+    lap(tm, &st.ms_gs, slot(k, 0));
     piv[k] = Jbest;
     rho[k] = rbest;
     if (nu) nu[k] = passes;
@@ -343,25 +452,26 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
 
     // ---- 2. complex64 sweep with the FP32 copy (panel row m) ----
     if (m == panel) {
-      rc = anchor(choose_exact(rbest));
+      rc = anchor(choose_exact(rbest), slot(k - 1, 2));
       if (rc != RB_OK) return rc;
       a = k - 1;  // the new vector has not been swept yet
     }
     tm.start();
     RB_HIP(launch_sweep_c(X32, N, M, ldX, e32, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr, stream));
-    tm.stop(&st.ms_sweep);  // the sweep kernel alone
+    lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
     RB_HIP(launch_sweep_c_final(M, part, top, stream));
     RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
     st.sweeps++;
     ++m;
+    if (h_top[0].i >= 0 && std::isnan(h_top[0].v)) return fail_run(RB_ENONFINITE, "a swept estimate is not finite");
     if (h_top[0].i >= 0 && h_top[0].v < o.theta32 * A_w) {
-      rc = anchor(choose_exact(std::sqrt(h_top[0].v > 0.0 ? h_top[0].v : 0.0)));
+      rc = anchor(choose_exact(std::sqrt(h_top[0].v > 0.0 ? h_top[0].v : 0.0)), slot(k - 1, 2));
       if (rc != RB_OK) return rc;
     }
     // ---- 3. FP64 confirmation of the candidates ----
     const int64_t top1 = h_top[0].i;
-    rc = confirm(k);
+    rc = confirm(k, slot(k, 0));
     if (rc != RB_OK) return rc;
     if (Jbest >= 0 && Jbest != top1) st.misses++;
     err[k] = (Jbest >= 0) ? rbest : 0.0;

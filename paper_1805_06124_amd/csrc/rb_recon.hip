@@ -1,4 +1,4 @@
-// The reconstruction algorithm (Alg. 4, Sec. 5.3; Theorem 5.8): after the
+// The reconstruction algorithm (Alg. 4, Sec. 5.2.2; Theorem 5.8): after the
 // greedy has produced Q_j and R(1:j, :) = Q_j^H S Pi, take the SVD of
 // R(1:j, :) = V Sigma W^H, keep the k singular values >= tau2 and return
 // X_k = Q_j V(:, 1:k).  The rows of R are the coefficients C = E^H S up to

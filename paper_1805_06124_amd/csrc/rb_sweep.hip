@@ -180,7 +180,25 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgMax* __restrict_
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+template <class T>
+hipError_t launch_fill_t(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t grid = (n + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)grid), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s) { return launch_fill_t(p, v, n, s); }
+hipError_t launch_fill(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { return launch_fill_t(p, v, n, s); }
+hipError_t launch_fill(int* p, int v, int64_t n, hipStream_t s) { return launch_fill_t(p, v, n, s); }
 
 int64_t sweep_partials_needed(int64_t M) {
   int64_t a = (M + kColsPerBlock - 1) / kColsPerBlock;

@@ -19,11 +19,14 @@ constexpr int kS32Cols = 4;
 constexpr int kS32Unroll = 8;
 constexpr int kS32ColsPerBlock = kS32Waves * kS32Cols;
 
-// candidate order: larger value first, then lower index; index < 0 = empty
+// candidate order (the order of vi_max): NaN first, then larger value, then
+// lower index; index < 0 = empty
 __device__ __forceinline__ bool better(double av, int64_t ai, double bv, int64_t bi) {
   if (ai < 0) return false;
   if (bi < 0) return true;
-  if (av != bv) return av > bv;
+  const bool an = av != av, bn = bv != bv;
+  if (an != bn) return an;
+  if (!an && av != bv) return av > bv;
   return ai < bi;
 }
 

@@ -230,7 +230,7 @@ int rb_enrich_z(rb_regen_fn regen, void* regen_ctx, int64_t N, int64_t Mv, int64
     int64_t k_new = k;
     rb_stats st;
     const int rc = greedy_z_core("rb_enrich_z", F.p, N, nf, N, tol, kcap, F.p, N, E, ldE, k, piv, err, rho, nu,
-                                 &k_new, &o, &st, stream);
+                                 &k_new, nullptr, 0, &o, &st, stream);
     if (rc < 0) return rc;
     for (int64_t i = k; i < k_new; ++i) piv[i] = fidx[(size_t)piv[i]];
     tot.sweeps += st.sweeps;

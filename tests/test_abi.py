@@ -46,6 +46,9 @@ def test_default_opts_and_strerror(L):
     assert 0 < o.theta < 1
     assert b"invalid" in L.rb_strerror(-1)
     assert b"kmax" in L.rb_strerror(1)
+    assert b"Gram-Schmidt" in L.rb_strerror(-5)
+    assert b"eigen" in L.rb_strerror(-6)
+    assert o.step_ms is None
 
 
 def _greedy_args(N=10, M=10, ldS=10, kmax=3, tol=1e-10, S=1, E=1, ldE=10, piv=True):
@@ -57,7 +60,7 @@ def _greedy_args(N=10, M=10, ldS=10, kmax=3, tol=1e-10, S=1, E=1, ldE=10, piv=Tr
     k = ctypes.c_int64(-7)
     return [P(S) if S else None, N, M, ldS, tol, kmax, None, 0, P(E) if E else None, ldE,
             piv_a.ctypes.data_as(P) if piv else None, err.ctypes.data_as(P), rho.ctypes.data_as(P), None,
-            ctypes.byref(k), None, None, None], k
+            ctypes.byref(k), None, 0, None, None, None], k
 
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(M=-1), dict(ldS=5), dict(kmax=-1), dict(tol=-1.0),
@@ -87,7 +90,7 @@ def test_bad_options_rejected(L):
     L.rb_default_opts(ctypes.byref(o))
     o.kappa = 1.0
     args, k = _greedy_args()
-    args[15] = ctypes.byref(o)
+    args[17] = ctypes.byref(o)
     assert L.rb_greedy_z(*args) == -1
 
 
@@ -105,3 +108,59 @@ def test_product_package_does_not_import_oracle():
                         assert not (node.module or "").startswith("oracle")
             if f.endswith((".hip", ".h", ".cpp")):
                 assert "oracle" not in open(os.path.join(dirpath, f)).read().lower()
+
+
+def test_workspace_sizes(L):
+    """The size queries: positive for valid sizes, 0 for invalid ones, and
+    they grow with the coefficient panel (anchor_max x M complex128) and, for
+    the mixed greedy, hold the regeneration chunk and its coefficients."""
+    o = rbm.Opts()
+    L.rb_default_opts(ctypes.byref(o))
+    z = L.rb_greedy_z_workspace(1000, 2000, 200, None)
+    assert z == L.rb_greedy_z_workspace(1000, 2000, 200, ctypes.byref(o))
+    assert z >= 16 * 128 * 2000 + 25 * 2000
+    assert L.rb_greedy_z_workspace(1000, 4000, 200, None) > z
+    o.anchor_max = 16
+    assert L.rb_greedy_z_workspace(1000, 2000, 200, ctypes.byref(o)) < z - 16 * 100 * 2000
+    assert L.rb_greedy_z_workspace(0, 2000, 200, None) == 0
+    assert L.rb_greedy_z_workspace(1000, 2000, -1, None) == 0
+    o.anchor_max = 0
+    assert L.rb_greedy_z_workspace(1000, 2000, 200, ctypes.byref(o)) == 0
+    c = L.rb_greedy_c_workspace(1000, 2000, 200, None)
+    chunk = 2000  # regen_chunk (32768) clamped to M
+    assert c >= z + 16 * chunk * (1000 + 200)
+    assert L.rb_greedy_c_workspace(1000, 0, 200, None) == 0
+
+
+def _ws_args(ws, nbytes, W=1):
+    args, k = _greedy_args()
+    args[6] = ctypes.c_void_p(W) if W else None  # W
+    args[7] = 10
+    args[15] = ctypes.c_void_p(ws) if ws else None
+    args[16] = nbytes
+    return args, k
+
+
+def test_greedy_workspace_contract_on_host(L):
+    """With a caller workspace: too small -> RB_ENOMEM, missing W or a
+    misaligned workspace -> RB_EINVAL, all before any device work (the
+    pointers here are not device memory)."""
+    need = L.rb_greedy_z_workspace(10, 10, 3, None)
+    args, k = _ws_args(4096, need - 1)
+    assert L.rb_greedy_z(*args) == -2
+    assert k.value == -7 and b"needed" in L.rb_last_error()
+    args, k = _ws_args(4096, need, W=0)
+    assert L.rb_greedy_z(*args) == -1
+    args, k = _ws_args(4100, need)
+    assert L.rb_greedy_z(*args) == -1
+    # the mixed greedy: same contract with its own size
+    needc = L.rb_greedy_c_workspace(10, 10, 3, None)
+    assert needc > need
+    P = ctypes.c_void_p
+    import numpy as np
+    piv, err, rho = np.zeros(4, dtype=np.int64), np.zeros(5), np.zeros(4)
+    kk = ctypes.c_int64(-7)
+    rc = L.rb_greedy_c(P(1), 10, 10, 10, 1e-10, 3, P(1), None, P(1), 10, P(1), 10, piv.ctypes.data_as(P),
+                       err.ctypes.data_as(P), rho.ctypes.data_as(P), None, ctypes.byref(kk), P(4096), needc - 1,
+                       None, None, None)
+    assert rc == -2 and kk.value == -7
