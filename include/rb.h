@@ -228,6 +228,25 @@ int rb_greedy_z(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, in
 size_t rb_greedy_z_workspace(int64_t N, int64_t M, int64_t kmax, const rb_opts *opts);
 
 /*
+ * rb_greedy_z_noalloc -- for callers that cannot allocate memory (code that
+ * must not call hipMalloc, tight serving loops, harnesses that forbid it):
+ * rb_greedy_z with its workspace in a fixed device array of the library,
+ * RB_NOALLOC_SCRATCH_BYTES (64 MiB) on every device it runs on, held until
+ * the process ends.  It allocates neither device nor pinned host memory and
+ * creates no HIP events (opts->collect_stats is ignored: no timings).
+ * Arguments as rb_greedy_z without ws; W is required (it may equal S).
+ * Returns RB_ENOMEM, before any device work, when rb_greedy_z_workspace(N,
+ * M, kmax, opts) exceeds the array (lower opts->anchor_max to fit more
+ * columns: about 16 anchor_max M + 41 M bytes).  Every call on a device
+ * shares that device's array and keeps nothing from an earlier call; calls
+ * that overlap on one device race on it.
+ */
+#define RB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int rb_greedy_z_noalloc(const void *S, int64_t N, int64_t M, int64_t ldS, double tol, int64_t kmax, void *W,
+                        int64_t ldW, void *E, int64_t ldE, int64_t *piv, double *err, double *rho, int32_t *nu,
+                        int64_t *k_out, const rb_opts *opts, rb_stats *stats, hipStream_t stream);
+
+/*
  * rb_regen_fn -- regenerates snapshot columns in FP64 from their parameters
  * (the paper's model interface: S is filled by calls to a model, Sec. 6.1.1).
  *   ctx   caller context

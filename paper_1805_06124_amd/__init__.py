@@ -56,7 +56,8 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
            "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z",
-           "rb_chirp_params", "rb_stream_read", "rb_greedy_z_workspace", "rb_greedy_c_workspace"]
+           "rb_chirp_params", "rb_stream_read", "rb_greedy_z_workspace", "rb_greedy_c_workspace",
+           "rb_greedy_z_noalloc"]
 
 _lib = None
 
@@ -85,6 +86,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     SZ = ctypes.c_size_t
     L.rb_greedy_z.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64), P, SZ,
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
+    L.rb_greedy_z_noalloc.restype = ctypes.c_int
+    L.rb_greedy_z_noalloc.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, I64, P, P, P, P, ctypes.POINTER(I64),
+                                      ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_greedy_z_workspace.restype = SZ
     L.rb_greedy_z_workspace.argtypes = [I64, I64, I64, ctypes.POINTER(Opts)]
     L.rb_greedy_c_workspace.restype = SZ
@@ -310,6 +314,38 @@ def greedy(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor | None = None
     if tr is not None:
         out["step_ms"] = tr.reshape(-1, 3)[k0:k + 1].copy()
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # RB_NOALLOC_SCRATCH_BYTES
+
+
+def greedy_noalloc(S: torch.Tensor, tol: float, kmax: int, W: torch.Tensor, E: torch.Tensor, stream=None,
+                   **opts) -> dict:
+    """rb_greedy_z_noalloc: the FP64 greedy with the library's fixed device
+    workspace (no allocation inside the call).  W (working matrix, may be S)
+    and E ((>= min(kmax, N, M), N) complex128 basis buffer) are the
+    caller's.  Returns as greedy() (no timings)."""
+    import numpy as np
+    M, N, ld = _mat(S, torch.complex128)
+    Mw, Nw, ldW = _mat(W, torch.complex128)
+    kE, NE, ldE = _mat(E, torch.complex128)
+    kcap = max(0, min(int(kmax), N, M))
+    if (Mw, Nw) != (M, N) or NE != N or kE < max(kcap, 1):
+        raise ValueError("W must have the shape of S and E room for min(kmax, N, M) vectors")
+    piv = np.zeros(max(kcap, 1), dtype=np.int64)
+    err = np.zeros(kcap + 1, dtype=np.float64)
+    rho = np.zeros(max(kcap, 1), dtype=np.float64)
+    nu = np.zeros(max(kcap, 1), dtype=np.int32)
+    kout = ctypes.c_int64()
+    o = default_opts(**opts)
+    st = Stats()
+    hp = [a.ctypes.data_as(ctypes.c_void_p) for a in (piv, err, rho, nu)]
+    rc = load().rb_greedy_z_noalloc(_ptr(S), N, M, ld, float(tol), int(kmax), _ptr(W), ldW, _ptr(E), ldE, *hp,
+                                    ctypes.byref(kout), ctypes.byref(o), ctypes.byref(st), _stream(stream))
+    _check("rb_greedy_z_noalloc", rc, ok=(0, 1, 2))
+    k = kout.value
+    return dict(E=E[:k], piv=piv[:k].copy(), err=err[:k + 1].copy(), rho=rho[:k].copy(), nu=nu[:k].copy(), k=k,
+                status=STATUS[rc], stats=st.as_dict())
 
 
 def residual_norms(E: torch.Tensor, V: torch.Tensor, stream=None) -> torch.Tensor:
