@@ -23,7 +23,11 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# RB_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the interpreter must then preload libasan and
+# libubsan; see tests/test_oracle_sanitized.py)
+SANITIZE = os.environ.get("RB_ORACLE_SANITIZE", "") == "1"
+LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "rb_oracle.c")
 
 STATUS = {0: "OK", 1: "KMAX", 2: "RANK", -1: "EINVAL", -2: "ENOMEM", -4: "ENONFINITE", -6: "EREPLAY"}
@@ -35,6 +39,9 @@ def build(force: bool = False) -> str:
         tmp = LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
                "-o", tmp, SRC_PATH, "-lm"]
+        if SANITIZE:
+            cmd[1:2] = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH

@@ -37,12 +37,14 @@ def _check_resume(g, ref, S_host, k0, theta=1e-3, am=128):
     n = k - k0
     A = float(oracle.sqnorms(S_host).max())
     res = 16 * (am + 1) * U / theta
+    # the oracle followed the same pivots to the same length (checked before
+    # its per-step records are indexed)
+    assert ref["k"] == k, (ref["k"], k, g["status"], ref["status"])
     for i in range(n):
         mine, mx = ref["pick"][i]
         phi = 16 * (k0 + i + 1) * U * np.sqrt(A)
         w = mx * (2e-9 + res) + 2 * np.sqrt(max(mx, 0.0)) * phi
         assert mine >= mx - w, (k0 + i, mine, mx, w)
-    assert ref["k"] == k, (ref["k"], k, g["status"], ref["status"])
     np.testing.assert_array_equal(ref["piv"], g["piv"])
     phis = 16 * (np.arange(k0, k + 1) + 1) * U * np.sqrt(A)
     tol_err = ref["err"] * (1e-10 + res / 2) + phis

@@ -57,3 +57,55 @@ def test_layout_and_init():
     assert 0 < np.abs(p[o:o + n]).max() <= np.sqrt(6 / 512)
     np.testing.assert_array_equal(ri.batch_indices(5, 1000, 100, 12)[:10].ravel().size, 1000)
     assert sorted(ri.batch_indices(5, 1000, 100, 10).ravel()) == list(range(1000))
+
+
+def _torch_net(p, din, h, dout):
+    """The same network as torch modules (nn.Linear holds W transposed)."""
+    P = mlp.unpack(p, din, h, dout)
+    layers = []
+    for i, (a, b) in enumerate([(din, h), (h, h), (h, h), (h, dout)]):
+        lin = torch.nn.Linear(a, b).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(P["W%d" % (i + 1)].T.copy()))
+            lin.bias.copy_(torch.from_numpy(P["b%d" % (i + 1)].copy()))
+        layers += [lin, torch.nn.Tanh()] if i < 3 else [lin]
+    return torch.nn.Sequential(*layers)
+
+
+def test_forward_and_backward_match_torch_autograd():
+    """FP64 forward and gradients against torch.nn modules and autograd on
+    the same weights (an independent implementation of the chain rule)."""
+    din, h, dout, B = 2, 16, 10, 33
+    rng = np.random.default_rng(4)
+    p = ri.mlp_init(5, din, h, dout).astype(np.float64) + 0.05 * rng.standard_normal(
+        ri.mlp_layout(din, h, dout)["total"])
+    X = rng.uniform(-1, 1, (B, din))
+    T = rng.standard_normal((B, dout))
+    Y, Hs = mlp.forward(p, X, din, h, dout, bf16_round=False)
+    _, dY = mlp.loss_and_grad_out(Y, T, bf16_round=False)
+    g = mlp.unpack(mlp.backward(p, X, Hs, dY, din, h, dout, bf16_round=False), din, h, dout)
+    net = _torch_net(p, din, h, dout)
+    Yt = net(torch.from_numpy(X))
+    np.testing.assert_allclose(Y, Yt.detach().numpy(), rtol=1e-13, atol=1e-15)
+    torch.nn.functional.mse_loss(Yt, torch.from_numpy(T)).backward()
+    lins = [m for m in net if isinstance(m, torch.nn.Linear)]
+    for i, lin in enumerate(lins):
+        np.testing.assert_allclose(g["W%d" % (i + 1)], lin.weight.grad.numpy().T, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(g["b%d" % (i + 1)], lin.bias.grad.numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_matches_torch_over_several_steps():
+    """Ten Adam steps on a varying gradient sequence against torch.optim.Adam
+    (bias-corrected, the same hyper-parameters)."""
+    rng = np.random.default_rng(6)
+    n = 50
+    w0 = rng.standard_normal(n)
+    grads = rng.standard_normal((10, n)) * np.exp(rng.uniform(-4, 2, (10, n)))
+    w, m, v = w0.copy(), np.zeros(n), np.zeros(n)
+    wt = torch.nn.Parameter(torch.from_numpy(w0.copy()))
+    opt = torch.optim.Adam([wt], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for s in range(10):
+        w, m, v = mlp.adam(w, grads[s], m, v, s + 1, 3e-3)
+        wt.grad = torch.from_numpy(grads[s].copy())
+        opt.step()
+        np.testing.assert_allclose(w, wt.detach().numpy(), rtol=1e-13, atol=1e-15)
