@@ -17,9 +17,16 @@ The JSON line also carries
   surrogate    : the learned coefficient surrogate trained on those
                  coefficients and evaluated on held-out parameters against
                  the plain projection of regenerated snapshots;
+  cfg4         : the larger complex64 family, 10,000 x 1,638,400 (131 GB),
+                 mixed greedy to tol with its own run count;
   cpu_baseline : the CPU oracle's Pythagorean greedy (the paper's own CPU
                  method) timed on this host on a column slice, scaled to the
-                 full column count (pivot search cost is linear in M).
+                 full column count (pivot search cost is linear in M), and
+                 both oracle forms on the small workload at 1 thread and at
+                 all threads.
+Timed greedy runs pass a caller workspace (no allocation inside the call).
+Per-step device times (orthogonalisation, sweep, re-anchoring) come from one
+further traced run of each leg; --trace-jsonl writes them one step a line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -91,7 +98,22 @@ def cpu_baseline(w, m_slice, steps, log):
     # does not scale with M and is small here
     per_step_full = per_step_slice * (w.M / m_slice)
     log("cpu oracle: %d steps on %d columns in %.2f s" % (k, m_slice, dt))
+    # both oracle forms on the small workload, at 1 thread and at all threads
+    ws_ = __import__("rb_inputs").WORKLOADS["chirp_small_c128"]
+    S1 = oracle.chirp(ws_.params(), ws_.N, ws_.flo, ws_.fhi)
+    nth = oracle.num_threads()
+    small = {}
+    for mode in ("explicit", "pythag"):
+        for th in (1, nth):
+            oracle.set_threads(th)
+            t1 = time.perf_counter()
+            r1 = oracle.greedy(S1, ws_.tol, ws_.kmax, mode=mode)
+            d1 = time.perf_counter() - t1
+            small["%s_%dthreads" % (mode, th)] = {"s": d1, "k": int(r1["k"]), "steps_per_s": r1["k"] / d1}
+            log("cpu oracle %s, %d threads, %s: k=%d in %.3f s" % (mode, th, ws_.name, r1["k"], d1))
+    oracle.set_threads(nth)
     return {"value": 1.0 / per_step_full, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "small_workload": dict(small, workload=ws_.name, N=ws_.N, M=ws_.M, tol=ws_.tol),
             "sample": "Pythagorean-form oracle greedy (Eq. (6.3)), first %d steps on a %d-column slice of the "
                       "%s workload (N=%d), %.1f s measured on %d threads of %s (%d logical CPUs visible), "
                       "scaled by M/M_slice=%.0f to the full %d columns"
@@ -192,6 +214,65 @@ def run_spread(runs):
     t = np.array([dt for dt, _ in runs], dtype=float)
     q1, med, q3 = np.percentile(t, [25, 50, 75])
     return {"run_times_s": [float(x) for x in t], "median_s": float(med), "iqr_s": float(q3 - q1)}
+
+
+def step_stats(trace, k, path=None, tag=""):
+    """Median and interquartile range of the per-step device times of one
+    traced greedy run (trace: (k+1, 3) ms of orthogonalisation, sweep and
+    re-anchoring per basis vector); optionally one JSON line per step."""
+    import numpy as np
+    t = np.asarray(trace[:k])
+    out = {}
+    for j, name in enumerate(("gs", "sweep")):
+        q1, med, q3 = np.percentile(t[:, j], [25, 50, 75])
+        out[name + "_ms"] = {"median": float(med), "iqr": float(q3 - q1), "total": float(t[:, j].sum())}
+    an = np.nonzero(t[:, 2] > 0)[0]
+    out["anchored_steps"] = [int(i) for i in an]
+    out["anchor_ms_per_anchored_step"] = [float(t[i, 2]) for i in an]
+    if path:
+        with open(path, "a") as f:
+            for i in range(k):
+                f.write(json.dumps({"leg": tag, "step": i, "gs_ms": float(t[i, 0]), "sweep_ms": float(t[i, 1]),
+                                    "anchor_ms": float(t[i, 2])}) + "\n")
+    return out
+
+
+def weak_greedy_ratio(rb, E, piv, rho, S64, tol, log):
+    """For each step i of a mixed run: rho_i (the confirmed pivot's exact
+    residual) over the largest FP64 residual of any unpivoted column against
+    the first i mixed basis vectors.  1 = the pivot was the true maximum;
+    below 1 = a weak-greedy step.  The maximum comes from C = E^H S64
+    (||s||^2 - sum |c|^2) while it is above 1e-10, and from explicit
+    residual norms (rb_residual_norms_z) below that."""
+    import numpy as np
+    import torch
+    k = E.shape[0]
+    C = rb.project(E, S64)
+    nrm = rb.colnorms(S64)
+    res2 = torch.empty((S64.shape[0], k), dtype=torch.float64, device=S64.device)
+    res2[:, 0] = nrm
+    if k > 1:
+        res2[:, 1:] = nrm[:, None] - torch.cumsum(C[:, :k - 1].abs() ** 2, dim=1)
+    del C
+    pv = torch.from_numpy(np.asarray(piv)).to(S64.device)
+    for l in range(k):
+        res2[pv[l], l + 1:] = -float("inf")
+    mx = res2.max(dim=0).values.cpu().numpy()
+    del res2
+    explicit = 0
+    for i in range(k):
+        if mx[i] < 1e-10:
+            r = rb.residual_norms(E[:i].contiguous(), S64) if i else torch.sqrt(nrm)
+            r[pv[:i]] = 0.0
+            mx[i] = float(r.max().item()) ** 2
+            explicit += 1
+    ratio = np.asarray(rho[:k]) / np.sqrt(np.maximum(mx, 1e-300))
+    log("weak-greedy ratio along the mixed pivots: min %.4f median %.6f, %d steps below 1 - 1e-6 "
+        "(%d maxima from explicit residuals)" % (ratio.min(), np.median(ratio), int(np.sum(ratio < 1 - 1e-6)),
+                                                  explicit))
+    return {"min": float(ratio.min()), "median": float(np.median(ratio)),
+            "steps_below_1": int(np.sum(ratio < 1 - 1e-6)), "steps_below_0.9": int(np.sum(ratio < 0.9)),
+            "explicit_steps": explicit}
 
 
 def orthogonality(E):
@@ -332,6 +413,47 @@ def validation_leg(rb, ri, w, E, tol, n_cols, log):
     return out
 
 
+def cfg4_leg(rb, ri, args, log):
+    """The larger complex64 family (10,000 x 1,638,400, 131 GB) with a
+    complex64 working matrix (262 GB together): the mixed greedy to tol,
+    timed over args.cfg4_steps runs after one warm-up, plus one traced run
+    for the sweep roofline and the per-step split."""
+    import torch
+    w = ri.WORKLOADS["chirp_10k_1638400_c64"]
+    P = torch.from_numpy(w.params()).to("cuda:0")
+    log("generating %s: N=%d M=%d (%.1f GB complex64)" % (w.name, w.N, w.M, 8 * w.N * w.M / 1e9))
+    S32 = rb.chirp_fill(P, w.N, w.flo, w.fhi, dtype=torch.complex64)
+    W32 = torch.empty_like(S32)
+    wsc = rb.workspace(w.N, w.M, w.kmax, mixed=True)
+    runs = timed_runs(lambda: rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=W32, ws=wsc), args.cfg4_steps, 1,
+                      log, "cfg4")
+    t_run = sum(dt for dt, _ in runs) / len(runs)
+    g = runs[-1][1]
+    gs = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=W32, ws=wsc, trace=True)
+    st = gs["stats"]
+    ms = st["ms_sweep"] / max(st["sweeps"], 1)
+    by = sweep32_bytes(w.N, w.M)
+    read = achievable_read(rb, S32)
+    out = {"workload": w.name, "N": w.N, "M": w.M, "storage": "complex64", "tol": w.tol, "kmax": w.kmax,
+           "value": sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), "unit": "steps/s",
+           "time_to_tol_s": t_run, "runs": run_spread(runs), "k": int(g["k"]), "status": g["status"],
+           "err_final": float(g["err"][-1]), "anchors": int(g["stats"]["anchors"]),
+           "exact_anchors": int(g["stats"]["regen_anchors"]), "misses": int(g["stats"]["misses"]),
+           "roofline": {"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "ms_per_launch": ms, "bytes_per_launch": by, "achievable_read_GBs": read,
+                        "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read},
+           "breakdown_ms": {"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
+                            "total": st["ms_total"]},
+           "per_step": step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "cfg4"),
+           "workspace_bytes": int(wsc.numel())}
+    log("cfg4: k=%d, %.3f s per run = %.1f steps/s; sweep %.3f ms = %.1f GB/s; anchors %.1f ms (%d, exact %d)" % (
+        g["k"], t_run, out["value"], ms, out["roofline"]["achieved"], st["ms_anchor"], st["anchors"],
+        st["regen_anchors"]))
+    del S32, W32, wsc, runs, g, gs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +471,9 @@ def main():
     ap.add_argument("--sur-heldout", type=int, default=100000)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB and 3 fused sweeps (for HBM counters)")
+    ap.add_argument("--no-cfg4", action="store_true")
+    ap.add_argument("--cfg4-steps", type=int, default=3)
+    ap.add_argument("--trace-jsonl", default=None, help="write per-step device times here (one JSON line a step)")
     ap.add_argument("--cpu-slice", type=int, default=51200)
     ap.add_argument("--cpu-steps", type=int, default=80)
     args = ap.parse_args()
@@ -390,11 +515,13 @@ def main():
         read_gbs = achievable_read(rb, S)
         log("plain streaming read of S: %.1f GB/s" % read_gbs)
         Wk = torch.empty_like(S)
-        runs = timed_runs(lambda: rb.greedy(S, tol, w.kmax, W=Wk), args.steps, args.warmup, log, "fp64")
+        wsz = rb.workspace(w.N, w.M, w.kmax)
+        runs = timed_runs(lambda: rb.greedy(S, tol, w.kmax, W=Wk, ws=wsz), args.steps, args.warmup, log, "fp64")
         t_run = sum(dt for dt, _ in runs) / len(runs)
         g = runs[-1][1]
-        gs = rb.greedy(S, tol, w.kmax, W=Wk, collect_stats=1)
+        gs = rb.greedy(S, tol, w.kmax, W=Wk, ws=wsz, trace=True)
         st = gs["stats"]
+        fp64_steps = step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "fp64")
         ms = st["ms_sweep"] / max(st["sweeps"], 1)
         by = sweep_bytes(w.N, w.M)
         read_after = achievable_read(rb, S)
@@ -413,10 +540,11 @@ def main():
                               "achievable_read_GBs": read_gbs,
                               "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read_gbs},
                     breakdown_ms={"sweep": st["ms_sweep"], "gs": st["ms_gs"], "anchor": st["ms_anchor"],
-                                  "total": st["ms_total"]})
+                                  "total": st["ms_total"]},
+                    per_step=fp64_steps, workspace_bytes=int(wsz.numel()))
         log("fp64 sweep: %.3f ms/launch, %.1f GB/s; gs %.1f ms, anchors %.1f ms (%d)" % (
             ms, fp64["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"]))
-        del Wk, gs, runs
+        del Wk, gs, runs, wsz
         torch.cuda.empty_cache()
         # projection of every snapshot on the final basis (FP64 matrix cores)
         E = g["E"].contiguous()
@@ -458,12 +586,14 @@ def main():
         read32 = achievable_read(rb, S32)
         log("plain streaming read of S32: %.1f GB/s" % read32)
         W32 = torch.empty_like(S32)
-        runs = timed_runs(lambda: rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32), args.steps,
+        wsc = rb.workspace(w.N, w.M, w.kmax, mixed=True)
+        runs = timed_runs(lambda: rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32, ws=wsc), args.steps,
                           args.warmup, log, "mixed")
         t_run = sum(dt for dt, _ in runs) / len(runs)
         g = runs[-1][1]
-        gs = rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32, collect_stats=1)
+        gs = rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32, ws=wsc, trace=True)
         st = gs["stats"]
+        mixed_steps = step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "mixed")
         ms = st["ms_sweep"] / max(st["sweeps"], 1)
         by = sweep32_bytes(w.N, w.M)
         read_after = achievable_read(rb, S32)
@@ -474,8 +604,7 @@ def main():
                      k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                      anchors=int(g["stats"]["anchors"]), exact_anchors=int(g["stats"]["regen_anchors"]),
                      misses=int(g["stats"]["misses"]), orthogonality=orthogonality(g["E"]),
-                     vs_fp64=(agreement(fp64_trace[0], fp64_trace[1], g["piv"], g["err"])
-                              if fp64_trace is not None else None),
+                     vs_fp64=None,
                      roofline={"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -484,16 +613,41 @@ def main():
                                "achievable_read_GBs": read32,
                                "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read32},
                      breakdown_ms={"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
-                                   "total": st["ms_total"]})
+                                   "total": st["ms_total"]},
+                     per_step=mixed_steps, workspace_bytes=int(wsc.numel()))
         log("mixed sweep: %.3f ms/launch, %.1f GB/s; confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (
             ms, mixed["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
-        if mixed["vs_fp64"] is not None:
-            a = mixed["vs_fp64"]
-            log("mixed vs fp64: pivot agreement %.3f (first divergence at step %s), common pivots %.3f, "
-                "relative error deviation median %.3g max %.3g, k %d vs %d" % (
-                    a["pivot_agreement"], a["first_divergence"], a["common_pivots"], a["err_rel_deviation_median"],
-                    a["err_rel_deviation_max"], a["k"], a["k_ref"]))
-        del S32, W32, g, gs, runs
+        del W32, gs, runs, wsc
+        torch.cuda.empty_cache()
+        if fp64_trace is not None:
+            # the FP64 greedy on the same columns, started from the mixed
+            # run's first vector: unit-norm columns tie at step 0, and the
+            # two storages break that tie differently, so both legs share
+            # step 0 and the comparison measures the FP32 sweep from step 1
+            S64 = rb.chirp_fill(params, w.N, w.flo, w.fhi)
+            W64 = torch.empty_like(S64)
+            Em = g["E"].contiguous()
+            gf = rb.greedy(S64, tol, w.kmax, W=W64, E0=Em[:1].contiguous())
+            del W64
+            torch.cuda.empty_cache()
+            piv_f = np.concatenate([g["piv"][:1], gf["piv"]])
+            err_f = np.concatenate([g["err"][:1], gf["err"]])
+            a = agreement(piv_f, err_f, g["piv"], g["err"])
+            a["fp64_first_vector"] = "the mixed run's e_1 (rb_greedy_resume_z from one vector)"
+            a["fp64_free_run"] = agreement(fp64_trace[0], fp64_trace[1], g["piv"], g["err"])
+            a["weak_greedy_ratio"] = weak_greedy_ratio(rb, Em, g["piv"], g["rho"], S64, tol, log)
+            mixed["vs_fp64"] = a
+            log("mixed vs fp64 (same first vector): pivot agreement %.3f (first divergence at step %s), common "
+                "pivots %.3f, relative error deviation median %.3g max %.3g, k %d vs %d" % (
+                    a["pivot_agreement"], a["first_divergence"], a["common_pivots"],
+                    a["err_rel_deviation_median"], a["err_rel_deviation_max"], a["k"], a["k_ref"]))
+            del S64, Em, gf
+        del S32, g
+        torch.cuda.empty_cache()
+
+    cfg4 = None
+    if not args.no_cfg4 and args.workload == "chirp_10k_409600_c128":
+        cfg4 = cfg4_leg(rb, ri, args, log)
         torch.cuda.empty_cache()
 
     cpu = None
@@ -513,6 +667,8 @@ def main():
                            "(basis vectors) per second, ms_per_step is the time of one run"},
         "roofline": main_leg["roofline"],
         "breakdown_ms": main_leg["breakdown_ms"],
+        "per_step": main_leg["per_step"],
+        "workspace_bytes": main_leg["workspace_bytes"],
         "runs": main_leg["runs"],
         "cpu_baseline": cpu,
     })
@@ -527,6 +683,8 @@ def main():
         out["surrogate"] = sur_out
     if val_out is not None:
         out["validation"] = val_out
+    if cfg4 is not None:
+        out["cfg4"] = cfg4
     print(json.dumps(out), flush=True)
 
 

@@ -226,3 +226,33 @@ def test_eim_full_size(rb):
     coef = np.linalg.solve(En[:, p].T, V[:, p].T)
     want = np.linalg.norm(V - coef.T @ En, axis=1)
     assert np.all(np.abs(got - want) <= 1e-7 * want + 1e-11), np.max(np.abs(got - want))
+
+
+def test_mixed_greedy_cfg4(rb):
+    """The largest matrix: 10,000 x 1,638,400 complex64 (131 GB; Mtot in
+    [20, 80], q in [1, 8]; half the paper's largest column count) with a
+    separate complex64 working matrix (262 GB for the two), greedy to
+    tol 1e-10 as the benchmark runs it.  Same checks as the 409,600-column
+    mixed run (every pivot's residual against the oracle's own column equals
+    rho_i; 192 sampled columns never exceed err_i / 0.9 and end below tol;
+    ||E^H E - I||_2 <= 2e-13)."""
+    torch.cuda.empty_cache()
+    w = ri.WORKLOADS["chirp_10k_1638400_c64"]
+    P_np = w.params()
+    P = torch.from_numpy(P_np).cuda()
+    print("cfg4: generating %d x %d complex64" % (w.N, w.M), flush=True)
+    S32 = rb.chirp_fill(P, w.N, w.flo, w.fhi, dtype=torch.complex64)
+    W32 = torch.empty_like(S32)
+    # generator parity on sampled columns (complex64 rounding of the FP64 values)
+    cols = np.random.default_rng(7).choice(w.M, 32, replace=False)
+    ref = oracle.chirp(P_np[cols], w.N, w.flo, w.fhi)
+    got = S32[torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 2.0 ** -24 * np.max(np.abs(ref)) * 1.01
+    print("cfg4: greedy", flush=True)
+    g = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=W32)
+    del S32, W32
+    torch.cuda.empty_cache()
+    print("cfg4: k=%d status=%s err=%.3e anchors=%d (exact %d)" % (
+        g["k"], g["status"], g["err"][-1], g["stats"]["anchors"], g["stats"]["regen_anchors"]), flush=True)
+    assert g["status"] == "OK" and 150 < g["k"] < w.kmax
+    _check_against_oracle(rb, w, P_np, g["E"].contiguous(), g, w.tol, weak=0.9)
