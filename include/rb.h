@@ -106,6 +106,12 @@ typedef struct rb_opts {
                          and of the re-anchorings that followed that sweep at
                          [3i+2]; [3k] may receive the final confirmation
                          that found the error below tol.  Default NULL. */
+  int32_t fuse;       /* FP64 greedy: 1 = when the next estimate is predicted
+                         to lose resolution, at most 16 vectors were swept
+                         since the last written anchoring and a norms-only
+                         re-anchoring is accurate enough, fold it into the
+                         next sweep (one read of the working matrix for
+                         both); 0 = separate passes only.  Default 1. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */
@@ -123,6 +129,8 @@ typedef struct rb_stats {
                             columns (the others deflate the stored columns) */
   int64_t misses;      /* mixed: steps whose confirmed pivot was not the
                           sweep's top candidate */
+  int64_t fused;       /* sweeps that also re-anchored (counted in sweeps
+                          and in anchors; their time is sweep time) */
 } rb_stats;
 
 void rb_default_opts(rb_opts *opts);

@@ -61,6 +61,7 @@ void rb_default_opts(rb_opts* o) {
   o->regen_chunk = 32768;
   o->certify = 2;
   o->step_ms = nullptr;
+  o->fuse = 1;
 }
 
 const char* rb_strerror(int status) {
@@ -159,8 +160,8 @@ struct ZScratch {
     nrm0 = c.take<double>(M);
     acc = c.take<double>(M);
     mask = c.take<uint8_t>(M);
-    part = c.take<ArgMax>(sweep_partials_needed(M));
-    res = c.take<ArgMax>(1);
+    part = c.take<ArgMax>(2 * sweep_partials_needed(M));  // the fused pass keeps two maxima per workgroup
+    res = c.take<ArgMax>(2);
     cpan = c.take<double2>((size_t)panel * (size_t)M);  // panel row r (vector a + r) at r*M
     v = c.take<double2>(N);
     g = c.take<double2>(kcap > 0 ? kcap : 1);
@@ -215,6 +216,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   if (k0 > kcap) return fail(RB_EINVAL, "the starting basis is larger than kmax or N");
   const int64_t panel = o.anchor_max;
   const int64_t np = sweep_partials_needed(M);
+  const int64_t np2 = 2 * np;  // capacity of the partials for a fused pass
 
   // scratch: the caller's workspace, or one allocation of the same layout
   ZScratch z;
@@ -232,10 +234,10 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   }
   z.carve(ws, N, M, std::min(kmax, N), panel);
   HostWords hw;
-  if (hw.init(d_ws.p != nullptr, 64) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
-  ArgMax* h_res = hw.at<ArgMax>(0);     // 16 B
-  double* h_sc = hw.at<double>(16);     // scalars
-  int* h_bad = hw.at<int>(48);
+  if (hw.init(d_ws.p != nullptr, 96) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
+  ArgMax* h_res = hw.at<ArgMax>(0);     // 2 x 16 B
+  double* h_sc = hw.at<double>(32);     // scalars
+  int* h_bad = hw.at<int>(64);
 
   rb_stats st;
   std::memset(&st, 0, sizeof st);
@@ -372,6 +374,35 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     const double r = std::sqrt(est > 0.0 ? est : 0.0);
     return 2.0 * (double)panel * 0x1p-53 * std::sqrt(A_X) <= 0.1 * o.theta * r;
   };
+  // Re-anchoring ahead of time, fused with the next sweep: when the next
+  // estimate is predicted (from the last step's decrease) to fall within a
+  // factor kFusePredict of the resolution threshold, the panel holds at most
+  // kFuseMaxM vectors and a norms-only anchoring is accurate enough, the
+  // next sweep also recomputes every column's residual norm against the
+  // panel, in the same read of X.  A step that still ends below the
+  // threshold falls back to the separate re-anchoring above.
+  constexpr double kFusePredict = 4.0;
+  bool fuse_next = false;
+  double est_prev = A_w;
+  // the fused pass with the newest vector (column k - 1 of E)
+  auto fused_sweep = [&](double* slot_ms, double* est_out, int64_t* J_out) -> int {
+    tm.start();
+    RB_HIP(launch_anchor_sweep(X, ldX, N, M, E + a * ldE, ldE, m, cpan, M, E + (k - 1) * ldE, nrm, acc, mask,
+                               cpan + m * M, part, np2, res, z.bad, stream));
+    ++m;
+    RB_HIP(hipMemcpyAsync(h_res, res, 2 * sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipStreamSynchronize(stream));
+    lap(tm, &st.ms_sweep, slot_ms);
+    st.sweeps++;
+    st.anchors++;
+    st.fused++;
+    if (*h_bad) return fail_run(RB_ENONFINITE, "a re-anchored column is not finite");
+    A_w = h_res[1].v;
+    *est_out = h_res[0].v;
+    *J_out = h_res[0].i;
+    return RB_OK;
+  };
 
   while (true) {
     if (err[k] < tol) {
@@ -450,17 +481,23 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
       // the new vector has not been swept yet: the panel restarts at it
       a = k - 1;
     }
-    tm.start();
-    RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr,
-                          stream));
-    lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
-    RB_HIP(launch_sweep_final(M, part, res, stream));
-    RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
-    RB_HIP(hipStreamSynchronize(stream));
-    st.sweeps++;
-    ++m;
-    double est_max = h_res->v;
-    J = h_res->i;
+    double est_max = 0.0;
+    if (fuse_next && m <= kFuseMaxM && norms_only_ok(est_prev)) {
+      int rc = fused_sweep(slot(k - 1, 1), &est_max, &J);
+      if (rc != RB_OK) return rc;
+    } else {
+      tm.start();
+      RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr,
+                            stream));
+      lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
+      RB_HIP(launch_sweep_final(M, part, res, stream));
+      RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+      RB_HIP(hipStreamSynchronize(stream));
+      st.sweeps++;
+      ++m;
+      est_max = h_res->v;
+      J = h_res->i;
+    }
     if (J >= 0 && std::isnan(est_max)) return fail_run(RB_ENONFINITE, "a swept estimate is not finite");
 
     // ---- 3. resolution check and error ----
@@ -471,6 +508,13 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
       J = h_res->i;
     }
     err[k] = (J >= 0) ? std::sqrt(est_max > 0.0 ? est_max : 0.0) : 0.0;
+    // ---- 4. fuse a re-anchoring into the next sweep? ----
+    {
+      const double e_now = est_max > 0.0 ? est_max : 0.0;
+      const double ratio = (est_prev > 0.0 && e_now < est_prev) ? e_now / est_prev : 1.0;
+      fuse_next = o.fuse != 0 && J >= 0 && e_now * ratio < kFusePredict * o.theta * A_w;
+      est_prev = e_now;
+    }
   }
   if (status == RB_KMAX && err[k] < tol) status = RB_OK;
   *k_out = k;

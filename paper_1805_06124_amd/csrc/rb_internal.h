@@ -173,6 +173,18 @@ hipError_t launch_resid(const double2* X, int64_t ldX, float2* W, int64_t ldW, i
 hipError_t launch_resid(const float2* X, int64_t ldX, float2* W, int64_t ldW, int64_t N, int64_t M,
                         const double2* E, int64_t ldE, int64_t m, const double2* C, int64_t cI, int64_t cJ,
                         double* nrm, int* bad, hipStream_t s);
+// Norms-only re-anchoring fused with the next sweep (FP64 working matrix
+// X, not written): against the m <= kFuseMaxM panel vectors E
+// (coefficients C(i, j) = Cp[i*ldCp + j]) nrm_j = ||x_j - E c_j||^2
+// explicitly, c_out[j] = e^H x_j, acc_j = |c_out[j]|^2; result[0] = the
+// masked argmax of nrm - acc, result[1] = the largest unmasked nrm.
+// partial needs 2 * anchor_sweep_partials(M) entries.
+constexpr int kFuseMaxM = 16;
+int64_t anchor_sweep_partials(int64_t M);
+hipError_t launch_anchor_sweep(const double2* X, int64_t ldX, int64_t N, int64_t M,
+                               const double2* E, int64_t ldE, int64_t m, const double2* Cp, int64_t ldCp,
+                               const double2* e, double* nrm, double* acc, const uint8_t* mask, double2* c_out,
+                               ArgMax* partial, int64_t npartial_cap, ArgMax* result, int* bad, hipStream_t s);
 // C = E^H S on FP64 matrix cores
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s);
