@@ -14,9 +14,11 @@ The JSON line also carries
                  FP64 basis), time to the same tol and its sweep roofline;
   projection   : C = E^H S of all snapshots on the final basis (FP64 matrix
                  cores) with its FLOP rate;
-  surrogate    : the learned coefficient surrogate trained on those
-                 coefficients and evaluated on held-out parameters against
-                 the plain projection of regenerated snapshots;
+  surrogate    : the learned coefficient surrogate (inputs: the parameters
+                 and the chirp phase at the basis's EIM nodes) trained on
+                 those coefficients and evaluated on held-out parameters
+                 against the plain projection of regenerated snapshots, with
+                 the throughput that counts the fallbacks;
   cfg4         : the larger complex64 family, 10,000 x 1,638,400 (131 GB),
                  mixed greedy to tol with its own run count;
   cpu_baseline : the CPU oracle's Pythagorean greedy (the paper's own CPU
@@ -136,8 +138,11 @@ def surrogate_leg(rb, ri, w, E, C, params, args, log):
     from paper_1805_06124_amd import surrogate as sg
     k = E.shape[0]
     T = sg.coef_targets(C)
-    sur = sg.Surrogate(k, ri.mlp_init(2024, 2, 256, 2 * k), ranges=(w.mlo, w.mhi, w.qlo, w.qhi),
-                       batch=args.sur_batch)
+    # inputs: mapped (Mtot, q) and the phase factors at the basis's EIM nodes
+    feats = sg.phase_features(E, w.flo, w.fhi)
+    din = feats["din"]
+    sur = sg.Surrogate(k, ri.mlp_init(2024, din, 256, 2 * k), ranges=(w.mlo, w.mhi, w.qlo, w.qhi),
+                       batch=args.sur_batch, features=feats)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = sur.train(params, T, args.sur_steps,
@@ -151,12 +156,18 @@ def surrogate_leg(rb, ri, w, E, C, params, args, log):
     log("surrogate: train %.1f s, loss %.3e -> %.3e; held-out median rel err %.3e; %.3g evals/s vs %.3g "
         "projections/s" % (t_train, hist[0][1], hist[-1][1], ev["relerr_median"], ev["surrogate_evals_per_s"],
                            ev["projections_per_s"]))
-    out = {"k": int(k), "layers": [2, 256, 256, 256, 2 * int(k)], "train_snapshots": w.M,
+    out = {"k": int(k), "layers": [din, 256, 256, 256, 2 * int(k)],
+           "inputs": "mapped (Mtot, q) and cos/-sin of the chirp phase at the %d EIM nodes of the basis" % (
+               (din - 2) // 2),
+           "train_snapshots": w.M,
            "steps": args.sur_steps, "batch": args.sur_batch, "train_s": t_train,
            "ms_per_train_step": 1e3 * t_train / args.sur_steps,
            "loss_first": hist[0][1], "loss_last": hist[-1][1], "heldout": ev,
-           "throughput_gain": ev["surrogate_evals_per_s"] / ev["projections_per_s"],
-           "served_within_1e-2": float(np.mean(e <= 1e-2)), "served_within_1e-6": float(np.mean(e <= 1e-6))}
+           "raw_eval_ratio": ev["surrogate_evals_per_s"] / ev["projections_per_s"],
+           "served_within_1e-2": float(np.mean(e <= 1e-2)), "served_within_1e-3": float(np.mean(e <= 1e-3)),
+           "served_within_1e-6": float(np.mean(e <= 1e-6))}
+    log("surrogate: served within 1e-2: %.4f, effective gain at 1e-2 %.2fx, at 1e-6 %.2fx" % (
+        out["served_within_1e-2"], ev["effective_gain"]["1e-02"], ev["effective_gain"]["1e-06"]))
     return out
 
 

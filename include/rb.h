@@ -23,8 +23,8 @@
  *  - Work is enqueued on the given stream (NULL = the default stream).
  *    Calls return after that work has completed (the greedy takes a host
  *    decision after every step), except those documented as "enqueued, not
- *    synchronised": rb_chirp_table, rb_chirp_regen, rb_chirp_params and
- *    rb_stream_read.
+ *    synchronised": rb_chirp_table, rb_chirp_regen, rb_chirp_params,
+ *    rb_stream_read and the surrogate's calls (rb_mlp_*, rb_coef_*).
  *  - Return value: an rb_status code.  Arguments are validated on the host
  *    before any device work; a call that fails later (a device error, a
  *    non-finite value found on the way) may have written part of its
@@ -542,7 +542,9 @@ int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64
  * W4 (hidden x dout), b4.  Inputs X: FP32 [batch][din]; outputs Y: FP32
  * [batch][dout].  The workspace ws (device, rb_mlp_workspace_bytes())
  * keeps the activations of the last forward for the backward pass and for
- * rb_mlp_loss.  1 <= din <= 4.
+ * rb_mlp_loss.  1 <= din <= 1024: up to 4 inputs the first layer runs on
+ * vector units, wider inputs take the BF16 matrix cores like the other
+ * layers.
  * ---------------------------------------------------------------------- */
 int64_t rb_mlp_param_count(int din, int hidden, int dout);
 size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout);
@@ -574,6 +576,21 @@ int rb_mlp_adam(float *p32, uint16_t *p16, const float *grad, float *m, float *v
  * [-1, 1]^2; T[b] = targets[idx[b]] (dout floats) if targets != NULL. */
 int rb_mlp_gather(const double *params, const float *targets, const int64_t *idx, int64_t batch, int dout,
                   const double *ranges, float *X, float *T, hipStream_t stream);
+
+/* Surrogate inputs that carry the snapshot's phase (the chirp family of
+ * rb_chirp_fill; the empirical-interpolation idea of Sec. 6.1: a snapshot is
+ * fixed by its values at k interpolation nodes, and on this family every
+ * snapshot has the same amplitude there, so its coefficients are a linear
+ * map of its phase factors at the nodes).  Row b of X (din = 2 + 2F floats)
+ * is built for sample idx[b]: the parameters mapped affinely from the box
+ * ranges (host, as rb_mlp_gather) onto [-1, 1]^2, then cos Psi(f_n) and
+ * -sin Psi(f_n) for each of the F grid rows n = rows[r] (device int64,
+ * typically the nodes of rb_eim_z), with table from rb_chirp_table for the
+ * grid.  T[b] = targets[idx[b]] (dout floats) if targets != NULL.
+ * 1 <= F, 2 + 2F <= 1024.  Enqueued, not synchronised. */
+int rb_mlp_phase_features(const double *params, const float *targets, const int64_t *idx, int64_t batch, int dout,
+                          const double *ranges, const int64_t *rows, int64_t F, const double *table, float *X,
+                          float *T, hipStream_t stream);
 
 /* Coefficients C (complex128, sample j at C[j*ldc .. j*ldc+k)) -> FP32
  * targets T[j] = [Re c_j; Im c_j] (2k floats per sample). */

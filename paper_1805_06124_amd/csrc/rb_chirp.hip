@@ -82,7 +82,54 @@ __global__ __launch_bounds__(kChirpThreads) void k_chirp(const double* __restric
   }
 }
 
+// Surrogate inputs of sample b (one workgroup): the affinely mapped
+// parameters and, at each of the F rows n = rows[r], the unit-modulus phase
+// factor exp(-i Psi(f_n)) of the snapshot (the chirp's value divided by its
+// amplitude, which is the same for every snapshot):
+//   X[b][0..1] = 2 (Mtot, q) - 1 on the parameter box, X[b][2 + 2r] =
+//   cos Psi(f_n), X[b][3 + 2r] = -sin Psi(f_n)  (FP64, rounded to FP32);
+//   T[b] = targets[idx[b]] (dout floats) when targets != NULL.
+__global__ __launch_bounds__(kChirpThreads) void k_phase_features(
+    const double* __restrict__ params, const float* __restrict__ targets, const int64_t* __restrict__ idx,
+    int dout, double mlo, double mhi, double qlo, double qhi, const int64_t* __restrict__ rows, int64_t F,
+    const double* __restrict__ tab, float* __restrict__ X, float* __restrict__ T) {
+  const int64_t b = blockIdx.x;
+  const int64_t pj = idx[b];
+  const int64_t din = 2 + 2 * F;
+  const double m = params[2 * pj], q = params[2 * pj + 1];
+  const double pm = kPi * m * kTsun;
+  const double eta = q / ((1.0 + q) * (1.0 + q));
+  const double a0 = 3.0 / (128.0 * eta);
+  const double A = a0 * pow(pm, -5.0 / 3.0);
+  const double B = a0 * (3715.0 / 756.0 + 55.0 * eta / 9.0) / pm;
+  float* x = X + b * din;
+  if (threadIdx.x == 0) {
+    x[0] = (float)(2.0 * (m - mlo) / (mhi - mlo) - 1.0);
+    x[1] = (float)(2.0 * (q - qlo) / (qhi - qlo) - 1.0);
+  }
+  for (int64_t r = threadIdx.x; r < F; r += kChirpThreads) {
+    const int64_t n = rows[r];
+    const double psi = -kPi / 4.0 + A * tab[3 * n + 1] + B * tab[3 * n + 2];
+    double sn, cs;
+    sincos(psi, &sn, &cs);
+    x[2 + 2 * r] = (float)cs;
+    x[3 + 2 * r] = (float)(-sn);
+  }
+  if (targets)
+    for (int t = threadIdx.x; t < dout; t += kChirpThreads) T[b * dout + t] = targets[pj * dout + t];
+}
+
 }  // namespace
+
+hipError_t launch_phase_features(const double* params, const float* targets, const int64_t* idx, int64_t batch,
+                                 int dout, const double* ranges, const int64_t* rows, int64_t F, const double* table,
+                                 float* X, float* T, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (batch > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_phase_features, dim3((unsigned)batch), dim3(kChirpThreads), 0, s, params, targets, idx, dout,
+                     ranges[0], ranges[1], ranges[2], ranges[3], rows, F, table, X, T);
+  return hipGetLastError();
+}
 
 hipError_t launch_chirp_table(double flo, double fhi, int64_t N, double* table, hipStream_t s) {
   hipLaunchKernelGGL(k_chirp_table, dim3(1), dim3(1024), 0, s, flo, fhi, N, table);

@@ -189,6 +189,11 @@ hipError_t launch_anchor_sweep(const double2* X, int64_t ldX, int64_t N, int64_t
 hipError_t launch_project_z(const double2* E, int64_t N, int64_t k, int64_t ldE, const double2* S, int64_t M,
                             int64_t ldS, double2* C, int64_t ldC, hipStream_t s);
 
+// surrogate inputs: mapped parameters and the phase factors at F rows
+// (X: batch x (2 + 2F) floats), targets gathered into T (see rb_chirp.hip)
+hipError_t launch_phase_features(const double* params, const float* targets, const int64_t* idx, int64_t batch,
+                                 int dout, const double* ranges, const int64_t* rows, int64_t F, const double* table,
+                                 float* X, float* T, hipStream_t s);
 // chirp row table (3 N doubles, see rb_chirp.hip) for launch_chirp_fill
 hipError_t launch_chirp_table(double flo, double fhi, int64_t N, double* table, hipStream_t s);
 // cols (device, may be NULL): output column j uses parameter set cols[j]

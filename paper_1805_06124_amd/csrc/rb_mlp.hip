@@ -1,10 +1,12 @@
-// Learned coefficient surrogate: an MLP (Mtot, q) -> [Re c; Im c] with
-// layers din -> hidden -> hidden -> hidden -> dout, tanh hidden activations,
-// BF16 weights and activations, FP32 accumulation and FP32 master weights.
-// The hidden and output layers run on BF16 matrix cores
-// (v_mfma_f32_16x16x32_bf16), their bias gradients ride along in the
-// weight-gradient products; the first layer (din = 2) and its gradients are
-// vector kernels.
+// Learned coefficient surrogate: an MLP (snapshot parameters and features
+// of them) -> [Re c; Im c] with layers din -> hidden -> hidden -> hidden ->
+// dout, tanh hidden activations, BF16 weights and activations, FP32
+// accumulation and FP32 master weights.  The hidden and output layers run on
+// BF16 matrix cores (v_mfma_f32_16x16x32_bf16), their bias gradients ride
+// along in the weight-gradient products.  A first layer with din <= 4
+// inputs and its gradients are vector kernels; a wider one (up to
+// kMaxDin inputs) takes the same matrix-core products as the others, on a
+// BF16 copy of the inputs.
 //
 // Parameter layout (FP32 master and BF16 copy share offsets), row-major
 // [in][out]:  W1 (din x h), b1 (h), W2 (h x h), b2, W3 (h x h), b3,
@@ -329,6 +331,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t
       }
 }
 
+// BF16 copy of the FP32 inputs (a wide first layer's matrix-core operand)
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, int64_t n, uint16_t* __restrict__ Xb) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) Xb[t] = f2bf(X[t]);
+}
+
 // first layer (din inputs, FP32 in): H1 = bf16(tanh(X W1 + b1))
 __global__ __launch_bounds__(256) void k_layer1_fwd(const float* __restrict__ X, int64_t B, int din,
                                                     const uint16_t* __restrict__ W1, const float* __restrict__ b1,
@@ -612,6 +619,17 @@ hipError_t gemm_splitk_partial(int64_t M, int64_t N, int64_t K, const uint16_t* 
   return launch_layouts<kEpiStore>(grid, g, s);
 }
 
+// inputs up to kNarrowDin: vector first layer; wider ones: matrix cores
+constexpr int kNarrowDin = 4;
+constexpr int kMaxDin = 1024;
+
+hipError_t to_bf16(const float* X, int64_t n, uint16_t* Xb, hipStream_t s) {
+  int64_t grid = (n + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)grid), dim3(256), 0, s, X, n, Xb);
+  return hipGetLastError();
+}
+
 struct Layout {
   int64_t W1, b1, W2, b2, W3, b3, W4, b4, total;
   Layout(int din, int h, int dout) {
@@ -649,25 +667,36 @@ using namespace rb;
 extern "C" {
 
 int64_t rb_mlp_param_count(int din, int hidden, int dout) {
-  if (din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return -1;
+  if (din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0) return -1;
   return Layout(din, hidden, dout).total;
 }
 
-size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
-  if (batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0) return 0;
+// column-sum partials (the vector first layer's gradients use din + 1 rows
+// of them; the loss uses one)
+static int64_t colsum_floats(int64_t batch, int din, int hidden, int dout) {
   const int64_t chunks = (batch + kColRows - 1) / kColRows;
-  const int64_t part = chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout);
-  // split-K partials of [dW2 db2 dW3 db3 dW4 db4], one contiguous block
+  const int dn = din <= kNarrowDin ? din : 0;
+  return chunks * (int64_t)(dn + 1) * (hidden > dout ? hidden : dout);
+}
+
+size_t rb_mlp_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
+  if (batch <= 0 || din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0) return 0;
+  const int64_t part = colsum_floats(batch, din, hidden, dout);
+  // split-K partials of [dW2 db2 dW3 db3 dW4 db4], one contiguous block,
+  // and of [dW1 db1] for a wide first layer
   const int64_t splitk = (int64_t)kSplitK * ((int64_t)(hidden + 1) * (2 * hidden + dout));
-  // H1..H3 and dZ (bf16), dY (bf16), Y (fp32), partial sums (column sums,
-  // then the split-K partials of the weight gradients)
-  return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout) * 2 + (size_t)batch * dout * 4 +
-         (size_t)(part + 4096 + splitk) * 4 + 1024;
+  const int64_t split1 = din > kNarrowDin ? (int64_t)kSplitK * (int64_t)(din + 1) * hidden : 0;
+  const int64_t xb = din > kNarrowDin ? batch * (int64_t)din : 0;  // BF16 inputs
+  // H1..H3 and dZ (bf16), dY (bf16), X (bf16), Y (fp32), partial sums
+  // (column sums, then the split-K partials of the weight gradients)
+  return (size_t)(3 * batch * hidden + 2 * batch * hidden + batch * dout + xb) * 2 + (size_t)batch * dout * 4 +
+         (size_t)(part + 4096 + splitk + split1) * 4 + 2048;
 }
 
 // Workspace carve-up (byte offsets) shared by forward and backward.
 static void carve(void* ws, int64_t batch, int din, int hidden, int dout, uint16_t** H, uint16_t** dz,
-                  uint16_t** dY, float** Y, float** part, float** splitp = nullptr) {
+                  uint16_t** dY, float** Y, float** part, float** splitp = nullptr, uint16_t** Xb = nullptr,
+                  float** split1 = nullptr) {
   char* p = static_cast<char*>(ws);
   for (int l = 0; l < 3; ++l) {
     H[l] = reinterpret_cast<uint16_t*>(p);
@@ -680,29 +709,37 @@ static void carve(void* ws, int64_t batch, int din, int hidden, int dout, uint16
   *dY = reinterpret_cast<uint16_t*>(p);
   p += (size_t)batch * dout * 2;
   p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~(uintptr_t)255);
+  if (Xb) *Xb = reinterpret_cast<uint16_t*>(p);
+  if (din > kNarrowDin) p += (size_t)batch * din * 2;
+  p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~(uintptr_t)255);
   *Y = reinterpret_cast<float*>(p);
   p += (size_t)batch * dout * 4;
   *part = reinterpret_cast<float*>(p);
-  if (splitp) {
-    const int64_t chunks = (batch + kColRows - 1) / kColRows;
-    *splitp = *part + chunks * (int64_t)(din + 1) * (hidden > dout ? hidden : dout) + 4096;
-  }
+  float* sp = *part + colsum_floats(batch, din, hidden, dout) + 4096;
+  if (splitp) *splitp = sp;
+  if (split1) *split1 = sp + (int64_t)kSplitK * ((int64_t)(hidden + 1) * (2 * hidden + dout));
 }
 
 int rb_mlp_forward(const float* p32, const uint16_t* p16, int din, int hidden, int dout, const float* X,
                    int64_t batch, float* Y, void* ws, hipStream_t stream) {
   last_error().clear();
-  if (!p32 || !p16 || !X || !ws || batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0)
+  if (!p32 || !p16 || !X || !ws || batch <= 0 || din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0)
     return set_error(RB_EINVAL, "rb_mlp_forward: bad arguments");
   const Layout L(din, hidden, dout);
-  uint16_t *H[3], *dz[2], *dY;
+  uint16_t *H[3], *dz[2], *dY, *Xb;
   float *Yw, *part;
-  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part);
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, nullptr, &Xb);
   if (!Y) Y = Yw;
-  const int64_t n1 = batch * hidden;
-  hipLaunchKernelGGL(k_layer1_fwd, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, stream, X, batch, din,
-                     p16 + L.W1, p32 + L.b1, hidden, H[0]);
-  RB_HIP(hipGetLastError());
+  if (din <= kNarrowDin) {
+    const int64_t n1 = batch * hidden;
+    hipLaunchKernelGGL(k_layer1_fwd, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, stream, X, batch, din,
+                       p16 + L.W1, p32 + L.b1, hidden, H[0]);
+    RB_HIP(hipGetLastError());
+  } else {
+    RB_HIP(to_bf16(X, batch * (int64_t)din, Xb, stream));
+    RB_HIP(gemm<kEpiBiasTanh>(batch, hidden, din, Xb, din, 1, p16 + L.W1, hidden, 1, nullptr, 0, p32 + L.b1, H[0],
+                              hidden, nullptr, 0, stream));
+  }
   RB_HIP(gemm<kEpiBiasTanh>(batch, hidden, hidden, H[0], hidden, 1, p16 + L.W2, hidden, 1, nullptr, 0, p32 + L.b2,
                             H[1], hidden, nullptr, 0, stream));
   RB_HIP(gemm<kEpiBiasTanh>(batch, hidden, hidden, H[1], hidden, 1, p16 + L.W3, hidden, 1, nullptr, 0, p32 + L.b3,
@@ -715,7 +752,7 @@ int rb_mlp_forward(const float* p32, const uint16_t* p16, int din, int hidden, i
 int rb_mlp_loss(const float* Y, const float* T, int64_t batch, int dout, uint16_t* dY_out, float* loss,
                 void* ws, int din, int hidden, hipStream_t stream) {
   last_error().clear();
-  if (!T || !loss || !ws || batch <= 0 || dout <= 0 || din <= 0 || din > 4 || hidden <= 0)
+  if (!T || !loss || !ws || batch <= 0 || dout <= 0 || din <= 0 || din > kMaxDin || hidden <= 0)
     return set_error(RB_EINVAL, "rb_mlp_loss: bad arguments");
   uint16_t *H[3], *dz[2], *dY;
   float *Yw, *part;
@@ -735,12 +772,12 @@ int rb_mlp_loss(const float* Y, const float* T, int64_t batch, int dout, uint16_
 int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, int dout, const float* X,
                     int64_t batch, const uint16_t* dY_in, float* grad, void* ws, hipStream_t stream) {
   last_error().clear();
-  if (!p32 || !p16 || !X || !grad || !ws || batch <= 0 || din <= 0 || din > 4 || hidden <= 0 || dout <= 0)
+  if (!p32 || !p16 || !X || !grad || !ws || batch <= 0 || din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0)
     return set_error(RB_EINVAL, "rb_mlp_backward: bad arguments");
   const Layout L(din, hidden, dout);
-  uint16_t *H[3], *dz[2], *dY;
-  float *Yw, *part, *splitp;
-  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp);
+  uint16_t *H[3], *dz[2], *dY, *Xb;
+  float *Yw, *part, *splitp, *split1;
+  carve(ws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp, &Xb, &split1);
   if (dY_in) dY = const_cast<uint16_t*>(dY_in);
   // Each bias directly follows its weight matrix in the layout (b_l = W_l +
   // rows x cols), and W2 b2 W3 b3 W4 b4 are one contiguous range: the three
@@ -768,7 +805,17 @@ int rb_mlp_backward(const float* p32, const uint16_t* p16, int din, int hidden, 
                      lenW, grad + L.W2);
   RB_HIP(hipGetLastError());
   // first layer: dW1 = X^T dZ1, db1 = colsum(dZ1)
-  RB_HIP(colsum(dz[0], batch, hidden, X, din, part, grad + L.b1, grad + L.W1, stream));
+  if (din <= kNarrowDin) {
+    RB_HIP(colsum(dz[0], batch, hidden, X, din, part, grad + L.b1, grad + L.W1, stream));
+  } else {
+    // the BF16 inputs of the forward pass on the same X, refreshed here
+    RB_HIP(to_bf16(X, batch * (int64_t)din, Xb, stream));
+    const int64_t len1 = (int64_t)(din + 1) * hidden;  // [dW1; db1], laid out like W1 b1
+    RB_HIP(gemm_splitk_partial(din, hidden, batch, Xb, 1, din, dz[0], hidden, 1, split1, len1, stream));
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((len1 + 255) / 256)), dim3(256), 0, stream, split1, splits,
+                       len1, grad + L.W1);
+    RB_HIP(hipGetLastError());
+  }
   return RB_OK;
 }
 
@@ -793,6 +840,19 @@ int rb_mlp_gather(const double* params, const float* targets, const int64_t* idx
   hipLaunchKernelGGL(k_gather, dim3((unsigned)batch), dim3(256), 0, stream, params, targets, idx, batch, dout,
                      ranges[0], ranges[1], ranges[2], ranges[3], X, T);
   RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_mlp_phase_features(const double* params, const float* targets, const int64_t* idx, int64_t batch, int dout,
+                          const double* ranges, const int64_t* rows, int64_t F, const double* table, float* X,
+                          float* T, hipStream_t stream) {
+  last_error().clear();
+  if (!params || !idx || !ranges || !rows || !table || !X || batch <= 0 || F < 1 || 2 + 2 * F > kMaxDin ||
+      (targets && (!T || dout <= 0)))
+    return set_error(RB_EINVAL, "rb_mlp_phase_features: bad arguments");
+  if (!(ranges[1] > ranges[0]) || !(ranges[3] > ranges[2]))
+    return set_error(RB_EINVAL, "rb_mlp_phase_features: bad ranges");
+  RB_HIP(launch_phase_features(params, targets, idx, batch, dout, ranges, rows, F, table, X, T, stream));
   return RB_OK;
 }
 

@@ -1,9 +1,17 @@
-"""Learned coefficient surrogate on the GPU: an MLP (Mtot, q) -> [Re c; Im c]
-for the projection coefficients c = E^H s of a snapshot on the greedy basis,
-trained on the method's own output (the projection of the training
-snapshots) with the library's BF16 matrix-core forward/backward kernels and
-Adam.  The plain projection of the regenerated snapshot checks each
-prediction and replaces it when its relative error exceeds a threshold.
+"""Learned coefficient surrogate on the GPU: an MLP from the snapshot
+parameters to [Re c; Im c], the projection coefficients c = E^H s of a
+snapshot on the greedy basis, trained on the method's own output (the
+projection of the training snapshots) with the library's BF16 matrix-core
+forward/backward kernels and Adam.  The plain projection of the regenerated
+snapshot checks each prediction and replaces it when its relative error
+exceeds a threshold.
+
+Inputs: either the mapped parameters (Mtot, q) alone, or those plus the
+snapshot's phase factors at the empirical-interpolation nodes of the basis
+(phase_features()).  On the chirp family the coefficients oscillate far too
+fast in (Mtot, q) for a network to follow from the parameters alone, while
+they are a linear map of the phase factors at the nodes (every snapshot has
+the same amplitude there).
 
 Everything numeric runs in librb.so (rb_mlp_*, rb_coef_*, rb_chirp_fill,
 rb_project_z); this module allocates device buffers and sequences the calls.
@@ -20,10 +28,28 @@ import torch
 from . import _check, _ptr, _stream, load, chirp_fill, project
 
 
+def phase_features(E: torch.Tensor, flo: float, fhi: float) -> dict:
+    """Inputs that carry the snapshot phase: the empirical-interpolation
+    nodes of the basis E (k, N) (rb_eim_z) and the chirp row table of the
+    grid.  din = 2 + 2k."""
+    from . import eim
+    ei = eim(E)
+    N = E.shape[1]
+    table = torch.empty(3 * N, dtype=torch.float64, device=E.device)
+    _check("rb_chirp_table", load().rb_chirp_table(float(flo), float(fhi), N, _ptr(table), _stream()))
+    rows = torch.from_numpy(np.ascontiguousarray(ei["nodes"][:ei["k"]], dtype=np.int64)).to(E.device)
+    return {"rows": rows, "table": table, "din": 2 + 2 * int(rows.numel())}
+
+
 class Surrogate:
     def __init__(self, k: int, init: np.ndarray, ranges, hidden: int = 256, batch: int = 4096, din: int = 2,
-                 device="cuda"):
+                 device="cuda", features: dict | None = None):
+        """features: None (inputs = mapped (Mtot, q), din = 2) or the dict of
+        phase_features() (din = 2 + 2 * number of nodes)."""
         L = load()
+        self.features = features
+        if features is not None:
+            din = features["din"]
         self.din, self.hidden, self.dout, self.batch = din, hidden, 2 * k, batch
         self.k = k
         n = L.rb_mlp_param_count(din, hidden, self.dout)
@@ -76,6 +102,12 @@ class Surrogate:
                                                  _ptr(self.v), self.n, lr, b1, b2, eps, self.step, _stream()))
 
     def gather(self, params: torch.Tensor, targets: torch.Tensor | None, idx: torch.Tensor, X, T):
+        if self.features is not None:
+            f = self.features
+            _check("rb_mlp_phase_features", load().rb_mlp_phase_features(
+                _ptr(params), _ptr(targets), _ptr(idx), idx.numel(), self.dout, self.ranges, _ptr(f["rows"]),
+                f["rows"].numel(), _ptr(f["table"]), _ptr(X), _ptr(T), _stream()))
+            return
         _check("rb_mlp_gather", load().rb_mlp_gather(_ptr(params), _ptr(targets), _ptr(idx), idx.numel(),
                                                      self.dout, self.ranges, _ptr(X), _ptr(T), _stream()))
 
@@ -167,11 +199,18 @@ def evaluate(sur: Surrogate, E: torch.Tensor, params: torch.Tensor, N: int, flo:
         t_sur += t2 - t1
         del S, C, Yh
     e = errs.cpu().numpy()
+    sur_rate, proj_rate = M / t_sur, M / t_proj
+    fb = {("%.0e" % t): float(np.mean(e > t)) for t in thresholds}
+    # every sample is predicted; those above the threshold are also
+    # regenerated and projected: time per sample 1/sur + f/proj
+    eff = {key: 1.0 / (1.0 / sur_rate + f / proj_rate) for key, f in fb.items()}
     return {
         "n": int(M),
         "relerr_median": float(np.median(e)), "relerr_p90": float(np.percentile(e, 90)),
         "relerr_max": float(e.max()), "relerr_min": float(e.min()),
-        "fallback_rate": {("%.0e" % t): float(np.mean(e > t)) for t in thresholds},
-        "surrogate_evals_per_s": M / t_sur, "projections_per_s": M / t_proj,
+        "fallback_rate": fb,
+        "surrogate_evals_per_s": sur_rate, "projections_per_s": proj_rate,
+        "effective_evals_per_s": eff,
+        "effective_gain": {key: v / proj_rate for key, v in eff.items()},
         "errors": e,
     }
