@@ -46,12 +46,12 @@ FP64_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each
 # scaled by the same counter's reading for a plain 4 GiB device copy (see
-# profiles/k_sweep_z_chirp_10k_409600_c128_hbm_counters.md), keyed by the
-# kernel source they were taken on: reported only while that source is
-# unchanged.
+# profiles/k_sweep_z_chirp_10k_409600_c128_hbm_counters.md), keyed by a hash
+# of the kernel's source file and the device header it inlines: reported
+# only while those sources are unchanged.
 MEASURED_TRAFFIC = {
-    ("k_sweep_z", "chirp_10k_409600_c128"): ("rb_sweep.hip", "2336c96802028e84", 65554830950),
-    ("k_sweep_c", "chirp_10k_409600_c64"): ("rb_sweep32.hip", "88b8e09ef3e038dc", 32789196151),
+    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_internal.h"), "9dc42129b4fb7b99", 65554852960),
+    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_internal.h"), "e2a92cdfe45d490d", 32789033483),
 }
 
 
@@ -60,12 +60,13 @@ def measured_traffic(kernel, workload):
     rec = MEASURED_TRAFFIC.get((kernel, workload))
     if rec is None:
         return None
-    src = os.path.join(ROOT, "paper_1805_06124_amd", "csrc", rec[0])
+    m = hashlib.sha256()
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for f in rec[0]:
+            m.update(open(os.path.join(ROOT, "paper_1805_06124_amd", "csrc", f), "rb").read())
     except OSError:
         return None
-    return rec[2] if h == rec[1] else None
+    return rec[2] if m.hexdigest()[:16] == rec[1] else None
 
 
 def sweep_bytes(N, M):
@@ -550,11 +551,14 @@ def main():
                               "ms_per_launch": ms, "bytes_per_launch": by,
                               "achievable_read_GBs": read_gbs,
                               "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read_gbs},
-                    breakdown_ms={"sweep": st["ms_sweep"], "gs": st["ms_gs"], "anchor": st["ms_anchor"],
-                                  "total": st["ms_total"]},
+                    breakdown_ms={"sweep": st["ms_sweep"], "fused_sweep_anchor": st["ms_fused"], "gs": st["ms_gs"],
+                                  "anchor": st["ms_anchor"], "total": st["ms_total"]},
+                    sweeps={"plain": int(st["sweeps"]), "fused_with_reanchoring": int(st["fused"])},
                     per_step=fp64_steps, workspace_bytes=int(wsz.numel()))
-        log("fp64 sweep: %.3f ms/launch, %.1f GB/s; gs %.1f ms, anchors %.1f ms (%d)" % (
-            ms, fp64["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"]))
+        log("fp64 sweep: %.3f ms/launch, %.1f GB/s (%d plain sweeps); %d fused sweep+re-anchoring passes %.1f ms; "
+            "gs %.1f ms, separate anchors %.1f ms (%d anchors in all)" % (
+                ms, fp64["roofline"]["achieved"], st["sweeps"], st["fused"], st["ms_fused"], st["ms_gs"],
+                st["ms_anchor"], st["anchors"]))
         del Wk, gs, runs, wsz
         torch.cuda.empty_cache()
         # projection of every snapshot on the final basis (FP64 matrix cores)

@@ -116,11 +116,12 @@ typedef struct rb_opts {
 
 /* Per-call statistics (host struct, optional). */
 typedef struct rb_stats {
-  int64_t sweeps;      /* fused sweeps run (one per basis vector after the
-                          first) */
+  int64_t sweeps;      /* plain sweeps run (one per basis vector, unless the
+                          vector's sweep was a fused pass, see fused) */
   int64_t anchors;     /* explicit re-anchorings (all kinds) */
   int64_t gs_passes;   /* Gram-Schmidt passes over all vectors */
-  double ms_sweep;     /* device time of the sweep kernels alone (collect_stats = 1) */
+  double ms_sweep;     /* device time of the plain sweep kernels alone
+                          (collect_stats = 1) */
   double ms_gs;        /* device time in orthogonalisation (and, mixed
                           precision, candidate confirmation) */
   double ms_anchor;    /* device time in re-anchoring */
@@ -129,8 +130,10 @@ typedef struct rb_stats {
                             columns (the others deflate the stored columns) */
   int64_t misses;      /* mixed: steps whose confirmed pivot was not the
                           sweep's top candidate */
-  int64_t fused;       /* sweeps that also re-anchored (counted in sweeps
-                          and in anchors; their time is sweep time) */
+  int64_t fused;       /* FP64: sweeps that also re-anchored (one read of
+                          the working matrix for both; counted in anchors,
+                          not in sweeps) */
+  double ms_fused;     /* device time of those fused passes */
 } rb_stats;
 
 void rb_default_opts(rb_opts *opts);
@@ -542,7 +545,10 @@ int rb_chirp_fill(const double *params, int64_t M, double flo, double fhi, int64
  * W4 (hidden x dout), b4.  Inputs X: FP32 [batch][din]; outputs Y: FP32
  * [batch][dout].  The workspace ws (device, rb_mlp_workspace_bytes())
  * keeps the activations of the last forward for the backward pass and for
- * rb_mlp_loss.  1 <= din <= 1024: up to 4 inputs the first layer runs on
+ * rb_mlp_loss.  It begins with the hidden activations H1, H2, H3 of the
+ * last forward, then dZ1 and dZ2 (the pre-activation gradients of hidden
+ * layers 1 and 2) of the last backward, each BF16 [batch][hidden], then dY
+ * of the last loss, BF16 [batch][dout].  1 <= din <= 1024: up to 4 inputs the first layer runs on
  * vector units, wider inputs take the BF16 matrix cores like the other
  * layers.
  * ---------------------------------------------------------------------- */

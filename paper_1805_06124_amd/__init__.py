@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("anchors", ctypes.c_int64), ("gs_passes", ctypes.c_int64),
                 ("ms_sweep", ctypes.c_double), ("ms_gs", ctypes.c_double), ("ms_anchor", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("regen_anchors", ctypes.c_int64), ("misses", ctypes.c_int64),
-                ("fused", ctypes.c_int64)]
+                ("fused", ctypes.c_int64), ("ms_fused", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -393,8 +393,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     RB_HIP(hipMemcpyAsync(h_res, res, 2 * sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipMemcpyAsync(h_bad, z.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
     RB_HIP(hipStreamSynchronize(stream));
-    lap(tm, &st.ms_sweep, slot_ms);
-    st.sweeps++;
+    lap(tm, &st.ms_fused, slot_ms);
     st.anchors++;
     st.fused++;
     if (*h_bad) return fail_run(RB_ENONFINITE, "a re-anchored column is not finite");

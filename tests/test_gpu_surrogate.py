@@ -226,3 +226,68 @@ def test_surrogate_trains_and_gains_over_projection(rb):
     assert np.isfinite(ev["errors"]).all()
     assert ev["relerr_median"] < 5e-2
     assert ev["surrogate_evals_per_s"] > 2 * ev["projections_per_s"]
+
+
+def _bf16_tensor(ws, off, rows, cols):
+    """BF16 bit patterns in the workspace at element offset off -> float64."""
+    u = ws.view(torch.int16)[off:off + rows * cols].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64).reshape(rows, cols)
+
+
+@pytest.mark.parametrize("din", [2, 284])
+def test_operand_for_operand(rb, din):
+    """Each product checked on the GPU's own BF16 operands (the workspace's
+    H1..H3, dZ1, dZ2 and dY), so only the FP32 summation order differs:
+    |d| <= 2e-5 of the sum of |terms| for outputs and weight gradients.
+    Activations recomputed in FP64 from the GPU's previous layer agree with
+    the GPU's BF16 values except where an FP32 pre-activation lies within
+    its summation error of a BF16 boundary: by at most one BF16 ulp plus
+    that error, in under 1% of the entries."""
+    k, B, h = 141, 4096, 256
+    sur, p, X, T, (din, h, dout) = _setup(rb, k=k, B=B, h=h, din=din)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    Y = sur.forward(Xd)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sur.loss_backward(Xd, Y, Td, loss)
+    torch.cuda.synchronize()
+    ws = sur.workspace(B)
+    H1, H2, H3 = (_bf16_tensor(ws, l * B * h, B, h) for l in range(3))
+    dZ1, dZ2 = _bf16_tensor(ws, 3 * B * h, B, h), _bf16_tensor(ws, 4 * B * h, B, h)
+    dY = _bf16_tensor(ws, 5 * B * h, B, dout)
+    P = mlp.unpack(p, din, h, dout)
+    W = {n: mlp.bf16(P[n]) for n in ("W1", "W2", "W3", "W4")}
+    g = mlp.unpack(sur.grad.cpu().numpy().astype(np.float64), din, h, dout)
+    Yn = Y.cpu().numpy().astype(np.float64)
+
+    def close(got, want, scale, what):
+        assert np.all(np.abs(got - want) <= 2e-5 * scale + 1e-30), (what, np.max(np.abs(got - want) / (scale + 1e-300)))
+
+    # output layer and the weight gradients whose operands survive
+    close(Yn, H3 @ W["W4"] + P["b4"], np.abs(H3) @ np.abs(W["W4"]) + np.abs(P["b4"]), "Y")
+    close(g["W4"], H3.T @ dY, np.abs(H3).T @ np.abs(dY), "dW4")
+    close(g["b4"], dY.sum(0), np.abs(dY).sum(0), "db4")
+    close(g["W2"], H1.T @ dZ2, np.abs(H1).T @ np.abs(dZ2), "dW2")
+    close(g["b2"], dZ2.sum(0), np.abs(dZ2).sum(0), "db2")
+    Xb = mlp.bf16(X) if din > 4 else X.astype(np.float64)  # a wide first layer reads BF16 inputs
+    close(g["W1"], Xb.T @ dZ1, np.abs(Xb).T @ np.abs(dZ1), "dW1")
+    close(g["b1"], dZ1.sum(0), np.abs(dZ1).sum(0), "db1")
+    # dZ3 is overwritten by dZ1; recomputed from the GPU's dY and H3 (it can
+    # differ from the GPU's own by rare one-ulp roundings), dW3 then agrees
+    # to the effect of those
+    dZ3 = mlp.bf16((dY @ W["W4"].T) * (1.0 - H3 * H3))
+    assert np.linalg.norm(g["W3"] - H2.T @ dZ3) <= 1e-4 * np.linalg.norm(H2.T @ dZ3)
+
+    def one_ulp(got, want, scale, what):
+        # one BF16 ulp of the rounded value, plus the FP32 summation error of
+        # its pre-activation (tanh' <= 1, 1 - h^2 <= 1), which can exceed an
+        # ulp where the pre-activation is a cancellation
+        d = np.abs(got - want)
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(want), 1e-300))) - 7)
+        assert np.all(d <= ulp * 1.0001 + 2e-5 * scale + 1e-300), what
+        assert np.mean(d > 0) < 1e-2, (what, np.mean(d > 0))
+
+    Xa = Xb if din > 4 else X.astype(np.float64)
+    one_ulp(H1, mlp.bf16(np.tanh(Xa @ W["W1"] + P["b1"])), np.abs(Xa) @ np.abs(W["W1"]) + np.abs(P["b1"]), "H1")
+    one_ulp(H2, mlp.bf16(np.tanh(H1 @ W["W2"] + P["b2"])), np.abs(H1) @ np.abs(W["W2"]) + np.abs(P["b2"]), "H2")
+    one_ulp(H3, mlp.bf16(np.tanh(H2 @ W["W3"] + P["b3"])), np.abs(H2) @ np.abs(W["W3"]) + np.abs(P["b3"]), "H3")
+    one_ulp(dZ1, mlp.bf16((dZ2 @ W["W2"].T) * (1.0 - H1 * H1)), np.abs(dZ2) @ np.abs(W["W2"]).T, "dZ1")
