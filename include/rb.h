@@ -442,9 +442,10 @@ int rb_enrich_z(rb_regen_fn regen, void *regen_ctx, int64_t N, int64_t Mv, int64
  *   Vout   device, complex128 j x j (ld j): the left singular vectors of C
  *          in the same order, or NULL (out)
  *   k_out  host: k (out)
- * Workspace: about 16 (j M + 5 j^2) bytes plus 32 KB of partial Gram tiles
- * per (tile pair, split).  Returns RB_ENOCONV if a Jacobi solve does not
- * settle within 60 sweeps.
+ * Workspace: about 16 (j M + 5 j^2) bytes, 16 KB of partial Gram tiles
+ * per (32-row tile pair, split) and, for j <= 141, a rotation log of
+ * 60 (j + 1)^2 / 2 x 32 bytes.  Returns RB_ENOCONV if a Jacobi solve does
+ * not settle within 60 sweeps.
  */
 int rb_reconstruct_z(const void *E, int64_t N, int64_t j, int64_t ldE, const void *C, int64_t M, int64_t ldC,
                      double tau2, void *X, int64_t ldX, double *sigma, void *Vout, int64_t *k_out,

@@ -98,7 +98,8 @@ def test_reconstruct_rows_not_graded(rb):
 
 
 def test_reconstruct_multi_tile(rb):
-    """j = 300 (five 64-row Gram tiles, ragged last tile) on a graded
+    """j = 300 (ten 32-row Gram tiles, ragged last tile; larger than the LDS
+    Jacobi takes, so the global-memory solve) on a graded
     Gaussian 400 x 600 input; several thresholds."""
     S = ri.graded(82, 400, 600, 0.99)
     g = oracle.greedy(S, 0.0, 300)
