@@ -599,6 +599,27 @@ int rb_mlp_phase_features(const double *params, const float *targets, const int6
                           const double *ranges, const int64_t *rows, int64_t F, const double *table, float *X,
                           float *T, hipStream_t stream);
 
+/* Whole training runs: steps Adam steps, step s on the batch of samples
+ * idx[s*batch .. (s+1)*batch) (device int64) with learning rate lr[s] (host
+ * float[steps]); the Adam step count runs from step0 + 1.  Each step
+ * gathers its inputs (rb_mlp_phase_features when rows != NULL, with
+ * din = 2 + 2F; else rb_mlp_gather, din = 2), then forward, loss, backward
+ * and Adam, all enqueued on stream without synchronising.  The result is
+ * bit-identical to calling those functions in turn; loss (device float[steps],
+ * or NULL) receives each step's loss.  For 4 < din <= 512, hidden a multiple
+ * of 64 up to 256 and dout <= 320 a step takes four launches besides the
+ * gather: one kernel carries kRB = 16 samples per workgroup through all
+ * layers forward and the loss gradient and dZ products backward with the
+ * activations in LDS, then the split-K weight-gradient products, then one
+ * kernel adds the splits and applies Adam.  Other shapes run the
+ * layer-by-layer functions.  ws: device, at least
+ * rb_mlp_train_workspace_bytes(); it begins with an rb_mlp workspace. */
+size_t rb_mlp_train_workspace_bytes(int64_t batch, int din, int hidden, int dout);
+int rb_mlp_train(float *p32, uint16_t *p16, float *m, float *v, int din, int hidden, int dout, const double *params,
+                 const float *targets, const int64_t *idx, int64_t batch, int64_t steps, int64_t step0,
+                 const float *lr, float beta1, float beta2, float eps, const double *ranges, const int64_t *rows,
+                 int64_t F, const double *table, float *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Coefficients C (complex128, sample j at C[j*ldc .. j*ldc+k)) -> FP32
  * targets T[j] = [Re c_j; Im c_j] (2k floats per sample). */
 int rb_coef_targets(const void *C, int64_t ldc, int64_t Mn, int k, float *T, hipStream_t stream);

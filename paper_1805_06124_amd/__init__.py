@@ -58,7 +58,7 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
            "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z",
            "rb_chirp_params", "rb_stream_read", "rb_greedy_z_workspace", "rb_greedy_c_workspace",
-           "rb_greedy_z_noalloc", "rb_mlp_phase_features"]
+           "rb_greedy_z_noalloc", "rb_mlp_phase_features", "rb_mlp_train", "rb_mlp_train_workspace_bytes"]
 
 _lib = None
 
@@ -142,6 +142,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_mlp_gather.argtypes = [P, P, P, I64, C_INT, P, P, P, P]
     L.rb_mlp_phase_features.restype = C_INT
     L.rb_mlp_phase_features.argtypes = [P, P, P, I64, C_INT, P, P, I64, P, P, P, P]
+    L.rb_mlp_train_workspace_bytes.restype = ctypes.c_size_t
+    L.rb_mlp_train_workspace_bytes.argtypes = [I64, C_INT, C_INT, C_INT]
+    L.rb_mlp_train.restype = C_INT
+    L.rb_mlp_train.argtypes = [P, P, P, P, C_INT, C_INT, C_INT, P, P, P, I64, I64, I64, P, F, F, F, P, P, I64, P,
+                               P, P, ctypes.c_size_t, P]
     L.rb_coef_targets.restype = C_INT
     L.rb_coef_targets.argtypes = [P, I64, I64, C_INT, P, P]
     L.rb_coef_relerr.restype = C_INT

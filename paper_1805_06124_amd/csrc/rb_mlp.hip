@@ -30,6 +30,18 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// The element-wise arithmetic shared by the layer-by-layer kernels and the
+// fused training step (one definition, so both round identically).
+__device__ __forceinline__ uint16_t act_tanh(float acc, float bias) { return f2bf(tanhf(acc + bias)); }
+__device__ __forceinline__ uint16_t act_dtanh(float acc, float h) { return f2bf(acc * (1.f - h * h)); }
+__device__ __forceinline__ uint16_t mse_grad(float d, float scale) { return f2bf(2.f * d * scale); }
+__device__ __forceinline__ void adam_update(float& w, float& m, float& v, float g, float lr, float b1, float b2,
+                                            float eps, float c1, float c2) {
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  w = w - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
 // ---------------------------------------------------------------- GEMM --
 // C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak],
 // B(k, n) = B[k*sbk + n*sbn], BF16 operands, FP32 accumulation.
@@ -222,27 +234,26 @@ __device__ __forceinline__ void colsum_chunk(const uint16_t (*sB)[kGKP], int ko,
 // the staged tiles, and store them as row M of C: C(M, n) = sum_k B(k, n).
 // That is the bias gradient beside a weight gradient dW = H^T dZ.
 template <int kEpi, int LA, int LB>
-__global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
-                                                   int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
-                                                   int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
-                                                   const float* __restrict__ bias, uint16_t* __restrict__ Cb,
-                                                   int64_t ldcb, const uint16_t* __restrict__ H, int64_t ldh,
-                                                   int vecA, int vecB, int64_t kc, int64_t cz, int csum) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
+__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
+                                          int64_t sam, int64_t sak, const uint16_t* __restrict__ B, int64_t sbk,
+                                          int64_t sbn, float* __restrict__ C, int64_t ldc,
+                                          const float* __restrict__ bias, uint16_t* __restrict__ Cb, int64_t ldcb,
+                                          const uint16_t* __restrict__ H, int64_t ldh, int vecA, int vecB,
+                                          int64_t kc, int64_t cz, int csum, int64_t bx, int64_t by, int64_t bz,
+                                          uint16_t (*sA)[kGKP], uint16_t (*sB)[kGKP]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * kGT, n0 = (int64_t)blockIdx.x * kGT;
+  const int64_t m0 = by * kGT, n0 = bx * kGT;
   f4v acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f4v){0.f, 0.f, 0.f, 0.f};
 
-  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t kb = bz * kc;
   const int64_t ke = (kb + kc < K) ? kb + kc : K;
-  if (kEpi == kEpiStore) C += (int64_t)blockIdx.z * cz;
-  const bool do_csum = kEpi == kEpiStore && csum && blockIdx.y == 0;
+  if (kEpi == kEpiStore) C += bz * cz;
+  const bool do_csum = kEpi == kEpiStore && csum && by == 0;
   float cs = 0.f;
   // the epilogue's operands (bias, or the activations for the tanh
   // derivative) do not depend on the product: load them first, from clamped
@@ -321,14 +332,66 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t
         if (kEpi == kEpiStore) {
           C[m * ldc + n] = v;
         } else if (kEpi == kEpiBiasTanh) {
-          Cb[m * ldcb + n] = f2bf(tanhf(v + bv[tb]));
+          Cb[m * ldcb + n] = act_tanh(v, bv[tb]);
         } else if (kEpi == kEpiBias) {
           C[m * ldc + n] = v + bv[tb];
         } else {
-          const float h = hv[ta][tb][r];
-          Cb[m * ldcb + n] = f2bf(v * (1.f - h * h));
+          Cb[m * ldcb + n] = act_dtanh(v, hv[ta][tb][r]);
         }
       }
+}
+
+
+template <int kEpi, int LA, int LB>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* __restrict__ A,
+                                                   int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
+                                                   int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ Cb,
+                                                   int64_t ldcb, const uint16_t* __restrict__ H, int64_t ldh,
+                                                   int vecA, int vecB, int64_t kc, int64_t cz, int csum) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
+  gemm_tile<kEpi, LA, LB>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Cb, ldcb, H, ldh, vecA, vecB, kc, cz, csum,
+                          blockIdx.x, blockIdx.y, blockIdx.z, sA, sB);
+}
+
+// Up to four split-K weight-gradient products (kEpiStore, with the bias row)
+// in one launch: workgroup b belongs to the product p with start[p] <= b <
+// start[p + 1] and takes the tile and split that k_gemm_bf16 would give it
+// with that product's grid (gx, gy, splits).  lay[p] selects the staging:
+// 0 both R16, 1 A R16 B R4, 2 A R4 B R16, 3 both R4, 4 guarded.
+struct GemmGroup {
+  int64_t M[4], N[4], K[4];
+  const uint16_t* A[4];
+  int64_t sam[4], sak[4];
+  const uint16_t* B[4];
+  int64_t sbk[4], sbn[4];
+  float* C[4];
+  int64_t ldc[4], kc[4], cz[4];
+  int vecA[4], vecB[4], lay[4], gx[4], gy[4];
+  int start[5];
+};
+
+__global__ __launch_bounds__(256) void k_gemm_group(GemmGroup g) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[kGT][kGKP];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[kGT][kGKP];
+  const int b = blockIdx.x;
+  int p = 0;
+  while (p < 3 && b >= g.start[p + 1]) ++p;
+  const int loc = b - g.start[p];
+  const int64_t bx = loc % g.gx[p], by = (loc / g.gx[p]) % g.gy[p], bz = loc / (g.gx[p] * g.gy[p]);
+#define RB_GEMM_CASE(LA, LB)                                                                                       \
+  gemm_tile<kEpiStore, LA, LB>(g.M[p], g.N[p], g.K[p], g.A[p], g.sam[p], g.sak[p], g.B[p], g.sbk[p], g.sbn[p],      \
+                               g.C[p], g.ldc[p], nullptr, nullptr, 0, nullptr, 0, g.vecA[p], g.vecB[p], g.kc[p],   \
+                               g.cz[p], 1, bx, by, bz, sA, sB)
+  switch (g.lay[p]) {
+    case 0: RB_GEMM_CASE(kR16, kR16); break;
+    case 1: RB_GEMM_CASE(kR16, kR4); break;
+    case 2: RB_GEMM_CASE(kR4, kR16); break;
+    case 3: RB_GEMM_CASE(kR4, kR4); break;
+    default: RB_GEMM_CASE(kGen, kGen); break;
+  }
+#undef RB_GEMM_CASE
 }
 
 // BF16 copy of the FP32 inputs (a wide first layer's matrix-core operand)
@@ -426,7 +489,7 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const 
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
     const float d = Y[t] - T[t];
     s += d * d;
-    dY[t] = f2bf(2.f * d * scale);
+    dY[t] = mse_grad(d, scale);
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   __shared__ float sh[4];
@@ -452,12 +515,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, uint16_t* _
                                               float eps, float c1, float c2) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
-  const float gt = g[t];
-  const float mt = b1 * m[t] + (1.f - b1) * gt;
-  const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+  float wt = w[t], mt = m[t], vt = v[t];
+  adam_update(wt, mt, vt, g[t], lr, b1, b2, eps, c1, c2);
   m[t] = mt;
   v[t] = vt;
-  const float wt = w[t] - lr * (mt / c1) / (sqrtf(vt / c2) + eps);
   w[t] = wt;
   w16[t] = f2bf(wt);
 }
@@ -619,6 +680,36 @@ hipError_t gemm_splitk_partial(int64_t M, int64_t N, int64_t K, const uint16_t* 
   return launch_layouts<kEpiStore>(grid, g, s);
 }
 
+// Product p of a grouped split-K launch, set up as gemm_splitk_partial would
+// launch it on its own; returns the workgroups it takes.
+int group_add(GemmGroup& g, int p, int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam, int64_t sak,
+              const uint16_t* B, int64_t sbk, int64_t sbn, float* P, int64_t cz) {
+  int splits;
+  const int64_t kc = splitk_chunk(K, &splits);
+  const int vecA = vec_mode(A, sam, sak), vecB = vec_mode(B, sbn, sbk);
+  const int la = fast_layout(vecA, M, K), lb = fast_layout(vecB, N, K);
+  g.M[p] = M;
+  g.N[p] = N;
+  g.K[p] = K;
+  g.A[p] = A;
+  g.sam[p] = sam;
+  g.sak[p] = sak;
+  g.B[p] = B;
+  g.sbk[p] = sbk;
+  g.sbn[p] = sbn;
+  g.C[p] = P;
+  g.ldc[p] = N;
+  g.kc[p] = kc;
+  g.cz[p] = cz;
+  g.vecA[p] = vecA;
+  g.vecB[p] = vecB;
+  g.lay[p] = (la == kR16 && lb == kR16) ? 0 : (la == kR16 && lb == kR4) ? 1 : (la == kR4 && lb == kR16) ? 2
+             : (la == kR4 && lb == kR4) ? 3 : 4;
+  g.gx[p] = (int)((N + kGT - 1) / kGT);
+  g.gy[p] = (int)((M + kGT - 1) / kGT);
+  return g.gx[p] * g.gy[p] * splits;
+}
+
 // inputs up to kNarrowDin: vector first layer; wider ones: matrix cores
 constexpr int kNarrowDin = 4;
 constexpr int kMaxDin = 1024;
@@ -656,6 +747,392 @@ hipError_t colsum(const uint16_t* D, int64_t B, int d, const float* X, int din, 
   hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, s, part, chunks, len, db, dW,
                      d);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------- fused training --
+// rb_mlp_train runs whole Adam steps, four launches each (inputs aside):
+//   k_mlp_rows   forward, loss gradient and the backward dZ products for
+//                kRB samples per workgroup, activations kept in LDS;
+//   split-K      the weight-gradient products (as rb_mlp_backward);
+//   k_adam_fused the split reduction, Adam and the BF16 weight copies.
+// The row kernel forms every value the layer-by-layer kernels form, from the
+// same operands, with the same MFMA sequence over k and the same element
+// arithmetic, so a fused step reproduces their bits (the loss value aside,
+// whose partial sums run in another order).  Its B operands come straight
+// from L2 into registers: each wave's share of a layer is loaded kFKC
+// k-steps at a time, so a hidden layer costs one memory latency.  For that
+// they need 8 consecutive k per output, which for the forward products is a
+// transposed copy of the weights ([out][in]); the backward products read the
+// weights as stored (W4 with its rows padded to a multiple of 8).
+constexpr int kRB = 16;        // samples per row-kernel workgroup
+constexpr int kMT = kRB / 16;  // MFMA row tiles per workgroup
+constexpr int kRowW = 8;       // waves per row-kernel workgroup
+constexpr int kRowT = 64 * kRowW;
+constexpr int kFMaxIn = 512;   // din rounded up to 32
+constexpr int kFMaxOut = 320;  // dout rounded up to 32
+constexpr int kFMaxH = 256;    // hidden: a multiple of 64
+constexpr int kFKC = 8;        // k-steps (of 32) whose operands are loaded together
+constexpr int kFMaxT = (kFMaxOut / 16 + kRowW - 1) / kRowW;  // output tiles of 16 columns per wave
+constexpr int kXq = kRB * kFMaxIn / kRowT;                    // input values staged per thread
+
+struct RowArgs {
+  const float* X;
+  const float* T;
+  int64_t batch;
+  int din, hid, dout, kin, kout;
+  const uint16_t *W1t, *W2t, *W3t, *W4t;  // [out][in]; row strides kin, hid, hid, hid
+  const uint16_t *W2, *W3, *W4b;          // [in][out]; row strides hid, hid, kout
+  const float *b1, *b2, *b3, *b4;
+  uint16_t *Xb, *H1, *H2, *H3, *dY, *dZ3, *dZ2, *dZ1;
+  float scale;
+  float* loss_part;
+};
+
+// acc[m][j] = sum over k < 32 ks of A(16 m + row, k) B(k, n) for this wave's
+// output tiles t = wave + kRowW j < ntile: A from LDS (row stride lda), B
+// lane l reads the 8 values k = 32 s + 8 (l / 16) .. + 7 of output
+// n = 16 t + l % 16 at Bp + n ldb + k, each used for all kMT row tiles.
+// Each workgroup reads every weight once per layer, so the samples per
+// workgroup set the weight traffic through L2.
+__device__ __forceinline__ void rows_mma(const uint16_t* sA, int lda, int ks, const uint16_t* __restrict__ Bp,
+                                         int ldb, int ntile, int wave, int lane, f4v (&acc)[kMT][kFMaxT]) {
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+    for (int j = 0; j < kFMaxT; ++j) acc[mt][j] = (f4v){0.f, 0.f, 0.f, 0.f};
+  const uint16_t* arow = sA + (lane & 15) * lda + 8 * (lane >> 4);
+  const uint16_t* brow = Bp + (int64_t)(lane & 15) * ldb + 8 * (lane >> 4);
+  for (int s0 = 0; s0 < ks; s0 += kFKC) {
+    bf16x8 b[kFKC][kFMaxT];
+#pragma unroll
+    for (int c = 0; c < kFKC; ++c)
+#pragma unroll
+      for (int j = 0; j < kFMaxT; ++j) {
+        const int s = s0 + c, t = wave + kRowW * j;
+        b[c][j] = (s < ks && t < ntile) ? *reinterpret_cast<const bf16x8*>(brow + (int64_t)16 * t * ldb + 32 * s)
+                                        : (bf16x8){};
+      }
+#pragma unroll
+    for (int c = 0; c < kFKC; ++c) {
+      const int s = s0 + c;
+      if (s >= ks) break;
+#pragma unroll
+      for (int mt = 0; mt < kMT; ++mt) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + 16 * mt * lda + 32 * s);
+#pragma unroll
+        for (int j = 0; j < kFMaxT; ++j)
+          if (wave + kRowW * j < ntile)
+            acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[c][j], acc[mt][j], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Everything the epilogues read from global memory (inputs, targets, biases)
+// is loaded at the start, all in flight together, so that only the weight
+// operands of each layer cost a memory latency.
+__global__ __launch_bounds__(kRowT) void k_mlp_rows(RowArgs a) {
+  constexpr int kLX = kFMaxIn + 8, kLH = kFMaxH + 8, kLD = kFMaxOut + 8;  // LDS row strides (values)
+  __shared__ __attribute__((aligned(16))) uint16_t sX[kRB * kLX];
+  __shared__ __attribute__((aligned(16))) uint16_t sH[3][kRB * kLH];
+  __shared__ __attribute__((aligned(16))) uint16_t sD[kRB * kLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[2][kRB * kLH];
+  __shared__ float sl[kRowW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kRB;
+  const int th = a.hid / 16, to = (a.dout + 15) / 16;
+  const int rbase = 4 * (lane >> 4);  // the rows of this lane in an MFMA result
+  // inputs: sample r0 + e / kin, value e % kin
+  float xv[kXq];
+#pragma unroll
+  for (int q = 0; q < kXq; ++q) {
+    const int e = tid + kRowT * q, r = e / a.kin, c = e - r * a.kin;
+    const int64_t row = r0 + r;
+    xv[q] = (r < kRB && row < a.batch && c < a.din) ? a.X[row * a.din + c] : 0.f;
+  }
+  // biases and targets of this lane's output columns
+  float bh[3][kFMaxT], b4v[kFMaxT], tv[kMT][kFMaxT][4];
+#pragma unroll
+  for (int j = 0; j < kFMaxT; ++j) {
+    const int t = wave + kRowW * j, col = 16 * t + (lane & 15);
+    const bool okh = t < th, oko = t < to && col < a.dout;
+    bh[0][j] = okh ? a.b1[col] : 0.f;
+    bh[1][j] = okh ? a.b2[col] : 0.f;
+    bh[2][j] = okh ? a.b3[col] : 0.f;
+    b4v[j] = oko ? a.b4[col] : 0.f;
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t g = r0 + 16 * mt + rbase + r;
+        tv[mt][j][r] = (oko && g < a.batch) ? a.T[g * a.dout + col] : 0.f;
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < kXq; ++q) {
+    const int e = tid + kRowT * q, r = e / a.kin, c = e - r * a.kin;
+    if (r < kRB) sX[r * kLX + c] = f2bf(xv[q]);
+  }
+  for (int e = tid; e < kRB * a.kout; e += kRowT) {
+    const int r = e / a.kout, c = e - r * a.kout;
+    if (c >= a.dout) sD[r * kLD + c] = 0;
+  }
+  __syncthreads();
+  f4v acc[kMT][kFMaxT];
+  // hidden layer: O = bf16(tanh(A W + b)) into LDS and global
+  auto hidden_out = [&](const float (&bias)[kFMaxT], uint16_t* sO) {
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+      for (int j = 0; j < kFMaxT; ++j) {
+        const int t = wave + kRowW * j;
+        if (t >= th) continue;
+        const int col = 16 * t + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sO[(16 * mt + rbase + r) * kLH + col] = act_tanh(acc[mt][j][r], bias[j]);
+      }
+  };
+  // backward: O = bf16(acc (1 - h^2)) with h the layer's activations
+  auto dtanh_out = [&](const uint16_t* sHl, uint16_t* sO) {
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+      for (int j = 0; j < kFMaxT; ++j) {
+        const int t = wave + kRowW * j;
+        if (t >= th) continue;
+        const int col = 16 * t + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + rbase + r;
+          sO[row * kLH + col] = act_dtanh(acc[mt][j][r], bf2f(sHl[row * kLH + col]));
+        }
+      }
+  };
+  // an LDS block of the layer outputs (kRB rows, n values each, row stride
+  // ld) to its rows of the global [batch][n] array: 16-byte pieces when the
+  // rows allow, else 4-byte or single values
+  auto copy_out = [&](const uint16_t* sO, int ld, uint16_t* __restrict__ gO, int n) {
+    const int w = n % 8 == 0 ? 8 : n % 2 == 0 ? 2 : 1;
+    const int per = n / w;
+    for (int e = tid; e < kRB * per; e += kRowT) {
+      const int r = e / per, c = (e - r * per) * w;
+      if (r0 + r >= a.batch) continue;
+      uint16_t* dst = gO + (r0 + r) * n + c;
+      const uint16_t* src = sO + r * ld + c;
+      if (w == 8)
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      else if (w == 2)
+        *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
+      else
+        *dst = *src;
+    }
+  };
+  copy_out(sX, kLX, a.Xb, a.din);
+  rows_mma(sX, kLX, a.kin / 32, a.W1t, a.kin, th, wave, lane, acc);
+  hidden_out(bh[0], sH[0]);
+  __syncthreads();
+  copy_out(sH[0], kLH, a.H1, a.hid);
+  rows_mma(sH[0], kLH, a.hid / 32, a.W2t, a.hid, th, wave, lane, acc);
+  hidden_out(bh[1], sH[1]);
+  __syncthreads();
+  copy_out(sH[1], kLH, a.H2, a.hid);
+  rows_mma(sH[1], kLH, a.hid / 32, a.W3t, a.hid, th, wave, lane, acc);
+  hidden_out(bh[2], sH[2]);
+  __syncthreads();
+  copy_out(sH[2], kLH, a.H3, a.hid);
+  // output layer, loss and dY = bf16(2 (Y - T) / (batch dout))
+  rows_mma(sH[2], kLH, a.hid / 32, a.W4t, a.hid, to, wave, lane, acc);
+  float ls = 0.f;
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+    for (int j = 0; j < kFMaxT; ++j) {
+      const int t = wave + kRowW * j;
+      if (t >= to) continue;
+      const int col = 16 * t + (lane & 15);
+      if (col >= a.dout) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mt + rbase + r;
+        uint16_t dy = 0;
+        if (r0 + row < a.batch) {
+          const float d = (acc[mt][j][r] + b4v[j]) - tv[mt][j][r];
+          ls += d * d;
+          dy = mse_grad(d, a.scale);
+        }
+        sD[row * kLD + col] = dy;
+      }
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o, 64);
+  if (lane == 0) sl[wave] = ls;
+  __syncthreads();
+  copy_out(sD, kLD, a.dY, a.dout);
+  if (tid == 0) {
+    float t = 0.f;
+    for (int w = 0; w < kRowW; ++w) t += sl[w];
+    a.loss_part[blockIdx.x] = t;
+  }
+  // dZ3 = (dY W4^T)(1 - H3^2), dZ2 = (dZ3 W3^T)(1 - H2^2), dZ1 = (dZ2 W2^T)(1 - H1^2)
+  rows_mma(sD, kLD, a.kout / 32, a.W4b, a.kout, th, wave, lane, acc);
+  dtanh_out(sH[2], sZ[0]);
+  __syncthreads();
+  copy_out(sZ[0], kLH, a.dZ3, a.hid);
+  rows_mma(sZ[0], kLH, a.hid / 32, a.W3, a.hid, th, wave, lane, acc);
+  dtanh_out(sH[1], sZ[1]);
+  __syncthreads();
+  copy_out(sZ[1], kLH, a.dZ2, a.hid);
+  rows_mma(sZ[1], kLH, a.hid / 32, a.W2, a.hid, th, wave, lane, acc);
+  dtanh_out(sH[0], sZ[0]);  // sZ[0] was last read before the barrier above
+  __syncthreads();
+  copy_out(sZ[0], kLH, a.dZ1, a.hid);
+}
+
+// The row kernel's weight copies from the BF16 weights: W1t (hid x kin),
+// W2t, W3t (hid x hid), W4t (kout x hid) transposed, W4b (hid x kout) as
+// stored; the padding is zero.
+__global__ __launch_bounds__(256) void k_fused_copies(const uint16_t* __restrict__ p16, int din, int hid, int dout,
+                                                      int kin, int kout, int64_t oW1, int64_t oW2, int64_t oW3,
+                                                      int64_t oW4, uint16_t* __restrict__ W1t,
+                                                      uint16_t* __restrict__ W2t, uint16_t* __restrict__ W3t,
+                                                      uint16_t* __restrict__ W4t, uint16_t* __restrict__ W4b) {
+  const int64_t n1 = (int64_t)hid * kin, n2 = (int64_t)hid * hid, n4 = (int64_t)kout * hid;
+  const int64_t total = n1 + 2 * n2 + 2 * n4;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int64_t f = e;
+    if (f < n1) {  // W1t[o][i] = W1[i][o]
+      const int64_t o = f / kin, i = f % kin;
+      W1t[f] = i < din ? p16[oW1 + i * hid + o] : 0;
+      continue;
+    }
+    f -= n1;
+    if (f < 2 * n2) {  // W2t, W3t
+      const bool three = f >= n2;
+      if (three) f -= n2;
+      const int64_t o = f / hid, i = f % hid;
+      (three ? W3t : W2t)[f] = p16[(three ? oW3 : oW2) + i * hid + o];
+      continue;
+    }
+    f -= 2 * n2;
+    if (f < n4) {  // W4t[o][i] = W4[i][o]
+      const int64_t o = f / hid, i = f % hid;
+      W4t[f] = o < dout ? p16[oW4 + i * dout + o] : 0;
+      continue;
+    }
+    f -= n4;  // W4b[i][o] = W4[i][o]
+    const int64_t i = f / kout, o = f % kout;
+    W4b[f] = o < dout ? p16[oW4 + i * dout + o] : 0;
+  }
+}
+
+// Split reduction, Adam and the BF16 copies for one step.  Workgroups
+// [0, tw[4]) take 32 x 32 tiles of W1..W4 (tile ranges tw[0..4]), the next
+// ceil((3 hidden + dout) / kAdamT) the biases b1 b2 b3 b4, the last one the
+// loss; one parameter a thread.  Every parameter's gradient is the sum over the
+// splits in order, as k_splitk_reduce forms it; a thread loads all the
+// splits and moments of its parameters before it updates any of them.
+struct AdamArgs {
+  float *p32, *m, *v;
+  uint16_t* p16;
+  const float* split1;  // [dW1; db1] partials, split stride len1
+  const float* splitp;  // [dW2 db2 dW3 db3 dW4 db4] partials, split stride lenW
+  int64_t len1, lenW;
+  int splits;
+  int din, hid, dout, kin, kout;
+  int64_t oW1, ob1, oW2, ob2, oW3, ob3, oW4, ob4;
+  uint16_t *W1t, *W2t, *W3t, *W4t, *W4b;
+  int tw[5];
+  int nbias_blocks;
+  float lr, beta1, beta2, eps, c1, c2;
+  const float* loss_part;
+  int nparts;
+  float scale;
+  float* loss_out;
+};
+
+// Adam on parameters i[q] (ok[q]); returns the updated weights in w
+template <int Q>
+__device__ __forceinline__ void adam_params(const AdamArgs& a, const int64_t (&i)[Q], const bool (&ok)[Q],
+                                            float (&w)[Q]) {
+  float g[Q][kSplitK], m[Q], v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const bool first = i[q] < a.oW2;  // W1, b1
+    const float* __restrict__ P = first ? a.split1 : a.splitp;
+    const int64_t len = first ? a.len1 : a.lenW, pi = i[q] - (first ? a.oW1 : a.oW2);
+#pragma unroll
+    for (int z = 0; z < kSplitK; ++z) g[q][z] = (ok[q] && z < a.splits) ? P[(int64_t)z * len + pi] : 0.f;
+    w[q] = ok[q] ? a.p32[i[q]] : 0.f;
+    m[q] = ok[q] ? a.m[i[q]] : 0.f;
+    v[q] = ok[q] ? a.v[i[q]] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (!ok[q]) continue;
+    float gs = 0.f;
+#pragma unroll
+    for (int z = 0; z < kSplitK; ++z)
+      if (z < a.splits) gs += g[q][z];
+    adam_update(w[q], m[q], v[q], gs, a.lr, a.beta1, a.beta2, a.eps, a.c1, a.c2);
+    a.m[i[q]] = m[q];
+    a.v[i[q]] = v[q];
+    a.p32[i[q]] = w[q];
+    a.p16[i[q]] = f2bf(w[q]);
+  }
+}
+
+constexpr int kAdamT = 1024;  // one parameter per thread: a 32 x 32 tile per workgroup
+
+__global__ __launch_bounds__(kAdamT) void k_adam_fused(AdamArgs a) {
+  __shared__ uint16_t tile[32][33];
+  __shared__ float sh[kAdamT / 64];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int blk = blockIdx.x;
+  if (blk >= a.tw[4] + a.nbias_blocks) {  // the loss
+    if (a.loss_out) {
+      float s = 0.f;
+      for (int t = tid; t < a.nparts; t += kAdamT) s += a.loss_part[t];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if ((tid & 63) == 0) sh[tid >> 6] = s;
+      __syncthreads();
+      if (tid == 0) {
+        float t = 0.f;
+        for (int w = 0; w < kAdamT / 64; ++w) t += sh[w];
+        *a.loss_out = t * a.scale;
+      }
+    }
+    return;
+  }
+  int64_t i[1];
+  bool ok[1];
+  float w[1];
+  if (blk >= a.tw[4]) {  // biases
+    const int e = (blk - a.tw[4]) * kAdamT + tid;
+    ok[0] = e < 3 * a.hid + a.dout;
+    i[0] = e < a.hid ? a.ob1 + e : e < 2 * a.hid ? a.ob2 + (e - a.hid) : e < 3 * a.hid ? a.ob3 + (e - 2 * a.hid)
+                                                                                         : a.ob4 + (e - 3 * a.hid);
+    adam_params<1>(a, i, ok, w);
+    return;
+  }
+  int l = 0;
+  while (blk >= a.tw[l + 1]) ++l;
+  const int nin = l == 0 ? a.din : a.hid, nout = l == 3 ? a.dout : a.hid;
+  const int64_t oW = l == 0 ? a.oW1 : l == 1 ? a.oW2 : l == 2 ? a.oW3 : a.oW4;
+  uint16_t* Wt = l == 0 ? a.W1t : l == 1 ? a.W2t : l == 2 ? a.W3t : a.W4t;
+  const int ldt = l == 0 ? a.kin : a.hid;
+  const int tcols = (nout + 31) / 32;
+  const int t = blk - a.tw[l];
+  const int i0 = (t / tcols) * 32, o0 = (t % tcols) * 32;
+  ok[0] = i0 + ty < nin && o0 + tx < nout;
+  i[0] = oW + (int64_t)(i0 + ty) * nout + o0 + tx;
+  adam_params<1>(a, i, ok, w);
+  const uint16_t h = ok[0] ? f2bf(w[0]) : (uint16_t)0;
+  if (l == 3 && ok[0]) a.W4b[(int64_t)(i0 + ty) * a.kout + o0 + tx] = h;
+  tile[ty][tx] = h;
+  __syncthreads();
+  const int oo = o0 + ty, ii = i0 + tx;
+  if (oo < nout && ii < nin) Wt[(int64_t)oo * ldt + ii] = tile[tx][ty];
 }
 
 }  // namespace
@@ -872,6 +1349,221 @@ int rb_coef_relerr(const float* Yh, const void* C, int64_t ldc, int64_t Mn, int 
   hipLaunchKernelGGL(k_coef_relerr, dim3((unsigned)((Mn + 3) / 4)), dim3(256), 0, stream, Yh,
                      static_cast<const double2*>(C), ldc, Mn, k, out);
   RB_HIP(hipGetLastError());
+  return RB_OK;
+}
+
+// ---- whole training runs ----
+
+namespace {
+
+struct TrainCarve {
+  uint16_t *dZ3, *W1t, *W2t, *W3t, *W4t, *W4b;
+  float *X, *T, *grad, *lpart, *lscratch;
+  void* mws;
+};
+
+// the layer-by-layer workspace first, then the fused step's buffers
+size_t train_carve(void* base, int64_t batch, int din, int hid, int dout, TrainCarve* c) {
+  const int kin = (din + 31) / 32 * 32, kout = (dout + 31) / 32 * 32;
+  const int64_t n = rb_mlp_param_count(din, hid, dout);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? static_cast<char*>(base) + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  char* mws = take(rb_mlp_workspace_bytes(batch, din, hid, dout));
+  char* dZ3 = take((size_t)batch * hid * 2);
+  char* X = take((size_t)batch * din * 4);
+  char* T = take((size_t)batch * dout * 4);
+  char* grad = take((size_t)n * 4);
+  char* W1t = take((size_t)hid * kin * 2);
+  char* W2t = take((size_t)hid * hid * 2);
+  char* W3t = take((size_t)hid * hid * 2);
+  char* W4t = take((size_t)kout * hid * 2);
+  char* W4b = take((size_t)hid * kout * 2);
+  char* lpart = take((size_t)((batch + kRB - 1) / kRB) * 4);
+  char* ls = take(4);
+  if (c) {
+    c->mws = mws;
+    c->dZ3 = reinterpret_cast<uint16_t*>(dZ3);
+    c->X = reinterpret_cast<float*>(X);
+    c->T = reinterpret_cast<float*>(T);
+    c->grad = reinterpret_cast<float*>(grad);
+    c->W1t = reinterpret_cast<uint16_t*>(W1t);
+    c->W2t = reinterpret_cast<uint16_t*>(W2t);
+    c->W3t = reinterpret_cast<uint16_t*>(W3t);
+    c->W4t = reinterpret_cast<uint16_t*>(W4t);
+    c->W4b = reinterpret_cast<uint16_t*>(W4b);
+    c->lpart = reinterpret_cast<float*>(lpart);
+    c->lscratch = reinterpret_cast<float*>(ls);
+  }
+  return off;
+}
+
+bool fused_ok(int din, int hid, int dout, const uint16_t* p16) {
+  const int kin = (din + 31) / 32 * 32, kout = (dout + 31) / 32 * 32;
+  if (din <= kNarrowDin || kin > kFMaxIn || hid % 64 != 0 || hid > kFMaxH || kout > kFMaxOut) return false;
+  const Layout L(din, hid, dout);
+  // the backward products read W2 and W3 in place, 16 bytes at a time
+  return (reinterpret_cast<uintptr_t>(p16 + L.W2) % 16 == 0) && (reinterpret_cast<uintptr_t>(p16 + L.W3) % 16 == 0);
+}
+
+}  // namespace
+
+size_t rb_mlp_train_workspace_bytes(int64_t batch, int din, int hidden, int dout) {
+  if (batch <= 0 || din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0) return 0;
+  return train_carve(nullptr, batch, din, hidden, dout, nullptr);
+}
+
+int rb_mlp_train(float* p32, uint16_t* p16, float* m, float* v, int din, int hidden, int dout, const double* params,
+                 const float* targets, const int64_t* idx, int64_t batch, int64_t steps, int64_t step0,
+                 const float* lr, float beta1, float beta2, float eps, const double* ranges, const int64_t* rows,
+                 int64_t F, const double* table, float* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  last_error().clear();
+  if (!p32 || !p16 || !m || !v || !params || !targets || !idx || !lr || !ranges || !ws || batch <= 0 || steps < 0 ||
+      step0 < 0 || din <= 0 || din > kMaxDin || hidden <= 0 || dout <= 0 || (rows && (!table || F < 1)))
+    return set_error(RB_EINVAL, "rb_mlp_train: bad arguments");
+  if (rows ? din != 2 + 2 * F : din != 2)
+    return set_error(RB_EINVAL, "rb_mlp_train: din must be 2 + 2F with phase features, else 2");
+  if (!(ranges[1] > ranges[0]) || !(ranges[3] > ranges[2])) return set_error(RB_EINVAL, "rb_mlp_train: bad ranges");
+  TrainCarve c;
+  const size_t need = train_carve(nullptr, batch, din, hidden, dout, nullptr);
+  if (ws_bytes < need)
+    return set_error(RB_ENOMEM, "rb_mlp_train: workspace of %zu bytes, %zu needed", ws_bytes, need);
+  train_carve(ws, batch, din, hidden, dout, &c);
+  const Layout L(din, hidden, dout);
+  const int64_t n = L.total;
+  const bool fused = fused_ok(din, hidden, dout, p16);
+  const int kin = (din + 31) / 32 * 32, kout = (dout + 31) / 32 * 32;
+  uint16_t *H[3], *dz[2], *dY, *Xb;
+  float *Yw, *part, *splitp, *split1;
+  carve(c.mws, batch, din, hidden, dout, H, dz, &dY, &Yw, &part, &splitp, &Xb, &split1);
+  if (fused && steps > 0) {
+    const int64_t total = (int64_t)hidden * kin + 2 * (int64_t)hidden * hidden + 2 * (int64_t)kout * hidden;
+    int64_t grid = (total + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_fused_copies, dim3((unsigned)grid), dim3(256), 0, stream, p16, din, hidden, dout, kin, kout,
+                       L.W1, L.W2, L.W3, L.W4, c.W1t, c.W2t, c.W3t, c.W4t, c.W4b);
+    RB_HIP(hipGetLastError());
+  }
+  const int64_t nrb = (batch + kRB - 1) / kRB;
+  const int64_t lenW = L.b4 + dout - L.W2, len1 = (int64_t)(din + 1) * hidden;
+  int splits;
+  (void)splitk_chunk(batch, &splits);
+  for (int64_t s = 0; s < steps; ++s) {
+    const int64_t* ix = idx + s * batch;
+    if (rows)
+      RB_HIP(launch_phase_features(params, targets, ix, batch, dout, ranges, rows, F, table, c.X, c.T, stream));
+    else
+      hipLaunchKernelGGL(k_gather, dim3((unsigned)batch), dim3(256), 0, stream, params, targets, ix, batch, dout,
+                         ranges[0], ranges[1], ranges[2], ranges[3], c.X, c.T);
+    RB_HIP(hipGetLastError());
+    const int64_t st = step0 + s + 1;
+    const float c1 = 1.f - powf(beta1, (float)st), c2 = 1.f - powf(beta2, (float)st);
+    if (!fused) {
+      float* lo = loss ? loss + s : c.lscratch;
+      int rc = rb_mlp_forward(p32, p16, din, hidden, dout, c.X, batch, nullptr, c.mws, stream);
+      if (rc == RB_OK) rc = rb_mlp_loss(nullptr, c.T, batch, dout, nullptr, lo, c.mws, din, hidden, stream);
+      if (rc == RB_OK) rc = rb_mlp_backward(p32, p16, din, hidden, dout, c.X, batch, nullptr, c.grad, c.mws, stream);
+      if (rc == RB_OK) rc = rb_mlp_adam(p32, p16, c.grad, m, v, n, lr[s], beta1, beta2, eps, st, stream);
+      if (rc != RB_OK) return rc;
+      continue;
+    }
+    RowArgs ra;
+    ra.X = c.X;
+    ra.T = c.T;
+    ra.batch = batch;
+    ra.din = din;
+    ra.hid = hidden;
+    ra.dout = dout;
+    ra.kin = kin;
+    ra.kout = kout;
+    ra.W1t = c.W1t;
+    ra.W2t = c.W2t;
+    ra.W3t = c.W3t;
+    ra.W4t = c.W4t;
+    ra.W2 = p16 + L.W2;
+    ra.W3 = p16 + L.W3;
+    ra.W4b = c.W4b;
+    ra.b1 = p32 + L.b1;
+    ra.b2 = p32 + L.b2;
+    ra.b3 = p32 + L.b3;
+    ra.b4 = p32 + L.b4;
+    ra.Xb = Xb;
+    ra.H1 = H[0];
+    ra.H2 = H[1];
+    ra.H3 = H[2];
+    ra.dY = dY;
+    ra.dZ3 = c.dZ3;
+    ra.dZ2 = dz[1];
+    ra.dZ1 = dz[0];
+    ra.scale = 1.f / (float)(batch * (int64_t)dout);
+    ra.loss_part = c.lpart;
+    hipLaunchKernelGGL(k_mlp_rows, dim3((unsigned)nrb), dim3(kRowT), 0, stream, ra);
+    RB_HIP(hipGetLastError());
+    // the four weight-gradient products (each with its bias gradient as an
+    // extra row, as rb_mlp_backward forms them) in one launch
+    GemmGroup gg;
+    gg.start[0] = 0;
+    gg.start[1] = gg.start[0] + group_add(gg, 0, hidden, dout, batch, H[2], 1, hidden, dY, dout, 1,
+                                          splitp + (L.W4 - L.W2), lenW);
+    gg.start[2] = gg.start[1] + group_add(gg, 1, hidden, hidden, batch, H[1], 1, hidden, c.dZ3, hidden, 1,
+                                          splitp + (L.W3 - L.W2), lenW);
+    gg.start[3] = gg.start[2] + group_add(gg, 2, hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, splitp,
+                                          lenW);
+    gg.start[4] = gg.start[3] + group_add(gg, 3, din, hidden, batch, Xb, 1, din, dz[0], hidden, 1, split1, len1);
+    hipLaunchKernelGGL(k_gemm_group, dim3((unsigned)gg.start[4]), dim3(256), 0, stream, gg);
+    RB_HIP(hipGetLastError());
+    AdamArgs aa;
+    aa.p32 = p32;
+    aa.m = m;
+    aa.v = v;
+    aa.p16 = p16;
+    aa.split1 = split1;
+    aa.splitp = splitp;
+    aa.len1 = len1;
+    aa.lenW = lenW;
+    aa.splits = splits;
+    aa.din = din;
+    aa.hid = hidden;
+    aa.dout = dout;
+    aa.kin = kin;
+    aa.kout = kout;
+    aa.oW1 = L.W1;
+    aa.ob1 = L.b1;
+    aa.oW2 = L.W2;
+    aa.ob2 = L.b2;
+    aa.oW3 = L.W3;
+    aa.ob3 = L.b3;
+    aa.oW4 = L.W4;
+    aa.ob4 = L.b4;
+    aa.W1t = c.W1t;
+    aa.W2t = c.W2t;
+    aa.W3t = c.W3t;
+    aa.W4t = c.W4t;
+    aa.W4b = c.W4b;
+    const int th = (hidden + 31) / 32, ti = (din + 31) / 32, tob = (dout + 31) / 32;
+    aa.tw[0] = 0;
+    aa.tw[1] = ti * th;
+    aa.tw[2] = aa.tw[1] + th * th;
+    aa.tw[3] = aa.tw[2] + th * th;
+    aa.tw[4] = aa.tw[3] + th * tob;
+    aa.nbias_blocks = (3 * hidden + dout + kAdamT - 1) / kAdamT;
+    aa.lr = lr[s];
+    aa.beta1 = beta1;
+    aa.beta2 = beta2;
+    aa.eps = eps;
+    aa.c1 = c1;
+    aa.c2 = c2;
+    aa.loss_part = c.lpart;
+    aa.nparts = (int)nrb;
+    aa.scale = ra.scale;
+    aa.loss_out = loss ? loss + s : nullptr;
+    hipLaunchKernelGGL(k_adam_fused, dim3((unsigned)(aa.tw[4] + aa.nbias_blocks + 1)), dim3(kAdamT), 0, stream,
+                       aa);
+    RB_HIP(hipGetLastError());
+  }
   return RB_OK;
 }
 

@@ -112,32 +112,48 @@ class Surrogate:
                                                      self.dout, self.ranges, _ptr(X), _ptr(T), _stream()))
 
     # -- training -----------------------------------------------------------
+    def train_steps(self, params: torch.Tensor, targets: torch.Tensor, idx: torch.Tensor, lr, loss=None):
+        """len(lr) Adam steps in one rb_mlp_train call: step s on the samples
+        idx[s] (device int64 (steps, batch)) with learning rate lr[s]; loss
+        (device float32 (steps,), optional) receives each step's loss."""
+        steps, B = idx.shape
+        lr = np.ascontiguousarray(lr, dtype=np.float32)
+        assert lr.shape == (steps,) and idx.is_contiguous()
+        L = load()
+        key = ("train", B)
+        if key not in self._ws:
+            nb = L.rb_mlp_train_workspace_bytes(B, self.din, self.hidden, self.dout)
+            self._ws[key] = torch.empty(nb, dtype=torch.uint8, device=self.dev)
+        ws = self._ws[key]
+        f = self.features
+        _check("rb_mlp_train", L.rb_mlp_train(
+            _ptr(self.p32), _ptr(self.p16), _ptr(self.m), _ptr(self.v), self.din, self.hidden, self.dout,
+            _ptr(params), _ptr(targets), _ptr(idx), B, steps, self.step, lr.ctypes.data_as(ctypes.c_void_p),
+            0.9, 0.999, 1e-8, self.ranges, _ptr(f["rows"]) if f is not None else None,
+            f["rows"].numel() if f is not None else 0, _ptr(f["table"]) if f is not None else None,
+            _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+        self.step += steps
+
     def train(self, params: torch.Tensor, targets: torch.Tensor, steps: int, index_fn, lr0: float = 1e-3,
               log_every: int = 0, log=None) -> list:
         """Adam with cosine-decayed learning rate.  index_fn(start, count)
         returns a (count, batch) int64 numpy array of sample indices."""
-        B = self.batch
-        X = torch.empty((B, self.din), dtype=torch.float32, device=self.dev)
-        T = torch.empty((B, self.dout), dtype=torch.float32, device=self.dev)
-        Y = torch.empty((B, self.dout), dtype=torch.float32, device=self.dev)
-        loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
         hist = []
         chunk = 500
+        loss = torch.zeros(chunk, dtype=torch.float32, device=self.dev)
         s = 0
         while s < steps:
             c = min(chunk, steps - s)
             idx = torch.from_numpy(index_fn(s, c)).to(self.dev)
-            for i in range(c):
-                lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * (s + i) / steps))
-                self.gather(params, targets, idx[i], X, T)
-                self.forward(X, Y)
-                self.loss_backward(X, Y, T, loss)
-                self.adam(lr)
-                if log_every and ((s + i) % log_every == 0 or s + i == steps - 1):
-                    lv = float(loss.item())
-                    hist.append((s + i, lv))
+            lr = 0.5 * lr0 * (1.0 + np.cos(np.pi * (s + np.arange(c)) / steps))
+            self.train_steps(params, targets, idx, lr, loss)
+            logged = [i for i in range(c) if log_every and ((s + i) % log_every == 0 or s + i == steps - 1)]
+            if logged:
+                lv = loss[:c].cpu().numpy()
+                for i in logged:
+                    hist.append((s + i, float(lv[i])))
                     if log:
-                        log("surrogate step %d loss %.3e" % (s + i, lv))
+                        log("surrogate step %d loss %.3e" % (s + i, float(lv[i])))
             s += c
         return hist
 
