@@ -54,7 +54,7 @@ void rb_default_opts(rb_opts* o) {
   o->kappa = 2.0;
   o->nu_max = 4;
   o->nu_min = 1;
-  o->theta = 1e-3;
+  o->theta = 1e-7;
   o->anchor_max = 128;
   o->collect_stats = 0;
   o->theta32 = 1e-4;

@@ -1,7 +1,7 @@
 """GPU parity of the HIP path against the CPU oracle on the same seeded
 inputs (the oracle never sees a value produced by the HIP path as input).
 
-Tolerances (derived in the design doc from the arithmetic):
+Tolerances (derived from the arithmetic):
   u = 2^-53,  A = max_j ||s_j||^2,  phi_k = 16 (k+1) u sqrt(A)
   resolution of Eq. (6.3) between anchorings: the estimated squared residual
   carries an absolute error <= 16 (anchor_max+1) u A_w and is trusted only
@@ -35,7 +35,12 @@ def _gpu_greedy_and_replay(rb, S_host, tol, kmax, **opts):
     return g, ref
 
 
-def _check_replay(g, ref, S_host, theta=1e-3, am=128):
+def _check_replay(g, ref, S_host, theta=None, am=128):
+    """theta: the resolution threshold the greedy ran with (None: the
+    library default)."""
+    if theta is None:
+        import paper_1805_06124_amd as rbm
+        theta = rbm.default_opts().theta
     k = g["k"]
     A = float(oracle.sqnorms(S_host).max())
     res = 16 * (am + 1) * U / theta
@@ -202,6 +207,15 @@ def test_greedy_working_matrix_modes(rb, mode):
     ref = oracle.greedy(S_host, 1e-10, 200, force=g["piv"])
     _check_replay(g, ref, S_host)
     assert g["stats"]["anchors"] >= 1
+
+
+def test_greedy_theta_1e3(rb):
+    """The coarser threshold theta = 1e-3 (more re-anchorings) with its
+    tighter resolution bound."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S_host = oracle.chirp(w.params(M=900), 800, w.flo, w.fhi)
+    g, ref = _gpu_greedy_and_replay(rb, S_host, 1e-10, 200, theta=1e-3)
+    _check_replay(g, ref, S_host, theta=1e-3)
 
 
 def test_greedy_anchor_options(rb):

@@ -32,7 +32,10 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _check_resume(g, ref, S_host, k0, theta=1e-3, am=128):
+def _check_resume(g, ref, S_host, k0, theta=None, am=128):
+    if theta is None:  # the resolution threshold of the library default
+        import paper_1805_06124_amd as rbm
+        theta = rbm.default_opts().theta
     k = g["k"]
     n = k - k0
     A = float(oracle.sqnorms(S_host).max())
