@@ -404,13 +404,20 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
   bool certified = false;
 
   // Bound on |est_j - true residual_j^2| for the stored columns since the
-  // last anchoring: FP32 coefficients (|dc| <= 9 u32 ||x_j||, so the m
-  // accumulated |c|^2 terms are off by <= 18 sqrt(m) u32 nrm_j) plus the
-  // stored-column perturbation P (|d ||r||^2| <= 2 ||r|| P + P^2).
+  // last anchoring.  The complex64 sweep sums, per lane and row tile, 8
+  // complex products (16 real ones per component) in FP32 with the FP32
+  // copy e32 of a unit vector, then adds the partials in FP64.  Per
+  // component the error is at most (gamma_16 + u32 (1 + gamma_16)) times
+  // sum_n |e_n| |x_n| <= ||x_j|| (Cauchy-Schwarz, ||e|| = 1), just over
+  // 17 u32 ||x_j||, so |dc| <= 17 sqrt(2) u32 ||x_j|| < 25 u32 ||x_j||; the m
+  // accumulated |c|^2 terms are off by at most sum (2 |c_i| |dc_i| +
+  // |dc_i|^2) <= 50 sqrt(m) u32 nrm_j + 625 m u32^2 nrm_j <= 51 sqrt(m) u32
+  // nrm_j (m <= anchor_max).  Plus the stored-column perturbation P
+  // (|d ||r||^2| <= 2 ||r|| P + P^2).
   auto est_bound = [&](double est) -> double {
     const double u32 = 0x1p-24;
     const double r = std::sqrt(est > 0.0 ? est : 0.0);
-    return 18.0 * std::sqrt((double)(m > 0 ? m : 1)) * u32 * A_w + 2.0 * r * P + P * P;
+    return 51.0 * std::sqrt((double)(m > 0 ? m : 1)) * u32 * A_w + 2.0 * r * P + P * P;
   };
 
   while (true) {
