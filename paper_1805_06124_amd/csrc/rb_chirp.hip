@@ -97,21 +97,16 @@ __global__ __launch_bounds__(kChirpThreads) void k_phase_features(
   const int64_t pj = idx[b];
   const int64_t din = 2 + 2 * F;
   const double m = params[2 * pj], q = params[2 * pj + 1];
-  const double pm = kPi * m * kTsun;
-  const double eta = q / ((1.0 + q) * (1.0 + q));
-  const double a0 = 3.0 / (128.0 * eta);
-  const double A = a0 * pow(pm, -5.0 / 3.0);
-  const double B = a0 * (3715.0 / 756.0 + 55.0 * eta / 9.0) / pm;
+  double A, B;
+  chirp_phase_coeffs(m, q, A, B);
   float* x = X + b * din;
   if (threadIdx.x == 0) {
-    x[0] = (float)(2.0 * (m - mlo) / (mhi - mlo) - 1.0);
-    x[1] = (float)(2.0 * (q - qlo) / (qhi - qlo) - 1.0);
+    x[0] = box_map(m, mlo, mhi);
+    x[1] = box_map(q, qlo, qhi);
   }
   for (int64_t r = threadIdx.x; r < F; r += kChirpThreads) {
-    const int64_t n = rows[r];
-    const double psi = -kPi / 4.0 + A * tab[3 * n + 1] + B * tab[3 * n + 2];
     double sn, cs;
-    sincos(psi, &sn, &cs);
+    sincos(chirp_phase(A, B, tab, rows[r]), &sn, &cs);
     x[2 + 2 * r] = (float)cs;
     x[3 + 2 * r] = (float)(-sn);
   }

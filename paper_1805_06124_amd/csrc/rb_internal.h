@@ -12,6 +12,31 @@ constexpr int kWave = 64;
 
 // ---------------------------------------------------------------- device --
 
+// Phase of the chirp family, Psi(f) = -pi/4 + A f^(-5/3) + B f^(-1) (the
+// leading and first post-Newtonian terms) for total mass m (solar masses)
+// and mass ratio q, evaluated from the grid table (tab[3n+1] = f_n^(-5/3),
+// tab[3n+2] = 1/f_n).  One definition for every kernel that forms the
+// surrogate's phase inputs, rounded step by step, so they agree bit for bit.
+constexpr double kChirpTsun = 4.925490947641267e-6;  // GM_sun / c^3 [s]
+constexpr double kChirpPi = 3.14159265358979323846;
+__device__ __forceinline__ void chirp_phase_coeffs(double m, double q, double& A, double& B) {
+#pragma clang fp contract(off)
+  const double pm = kChirpPi * m * kChirpTsun;
+  const double eta = q / ((1.0 + q) * (1.0 + q));
+  const double a0 = 3.0 / (128.0 * eta);
+  A = a0 * pow(pm, -5.0 / 3.0);
+  B = a0 * (3715.0 / 756.0 + 55.0 * eta / 9.0) / pm;
+}
+__device__ __forceinline__ double chirp_phase(double A, double B, const double* tab, int64_t n) {
+#pragma clang fp contract(off)
+  return -kChirpPi / 4.0 + A * tab[3 * n + 1] + B * tab[3 * n + 2];
+}
+// the surrogate's inputs of a sample: the parameters mapped onto [-1, 1]
+__device__ __forceinline__ float box_map(double v, double lo, double hi) {
+#pragma clang fp contract(off)
+  return (float)(2.0 * (v - lo) / (hi - lo) - 1.0);
+}
+
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 

@@ -771,13 +771,20 @@ constexpr int kRowT = 64 * kRowW;
 constexpr int kFMaxIn = 512;   // din rounded up to 32
 constexpr int kFMaxOut = 320;  // dout rounded up to 32
 constexpr int kFMaxH = 256;    // hidden: a multiple of 64
-constexpr int kFKC = 8;        // k-steps (of 32) whose operands are loaded together
+constexpr int kFKC = 9;        // k-steps (of 32) whose operands are loaded together (din, dout <= 288 in one)
 constexpr int kFMaxT = (kFMaxOut / 16 + kRowW - 1) / kRowW;  // output tiles of 16 columns per wave
-constexpr int kXq = kRB * kFMaxIn / kRowT;                    // input values staged per thread
 
 struct RowArgs {
-  const float* X;
-  const float* T;
+  // inputs of the step's samples idx[0 .. batch): the parameters mapped onto
+  // [-1, 1]^2 and the phase factors at the F grid rows `rows` (table `tab`);
+  // targets gathered from `targets` (dout floats per sample)
+  const double* params;
+  const float* targets;
+  const int64_t* idx;
+  const int64_t* rows;
+  const double* tab;
+  int64_t F;
+  double mlo, mhi, qlo, qhi;
   int64_t batch;
   int din, hid, dout, kin, kout;
   const uint16_t *W1t, *W2t, *W3t, *W4t;  // [out][in]; row strides kin, hid, hid, hid
@@ -842,13 +849,50 @@ __global__ __launch_bounds__(kRowT) void k_mlp_rows(RowArgs a) {
   const int64_t r0 = (int64_t)blockIdx.x * kRB;
   const int th = a.hid / 16, to = (a.dout + 15) / 16;
   const int rbase = 4 * (lane >> 4);  // the rows of this lane in an MFMA result
-  // inputs: sample r0 + e / kin, value e % kin
-  float xv[kXq];
-#pragma unroll
-  for (int q = 0; q < kXq; ++q) {
-    const int e = tid + kRowT * q, r = e / a.kin, c = e - r * a.kin;
-    const int64_t row = r0 + r;
-    xv[q] = (r < kRB && row < a.batch && c < a.din) ? a.X[row * a.din + c] : 0.f;
+  // inputs: the samples' parameter coefficients first (one thread per
+  // sample), then the phase factors, written to LDS as BF16 (zero past din
+  // and past the batch)
+  __shared__ double sA[kRB], sB[kRB];
+  __shared__ int64_t spj[kRB];
+  if (tid < kRB) {
+    const int64_t g = r0 + tid;
+    double A = 0.0, B = 0.0;
+    int64_t pj = -1;
+    uint16_t x0 = 0, x1 = 0;
+    if (g < a.batch) {
+      pj = a.idx[g];
+      const double m = a.params[2 * pj], q = a.params[2 * pj + 1];
+      chirp_phase_coeffs(m, q, A, B);
+      x0 = f2bf(box_map(m, a.mlo, a.mhi));
+      x1 = f2bf(box_map(q, a.qlo, a.qhi));
+    }
+    sA[tid] = A;
+    sB[tid] = B;
+    spj[tid] = pj;
+    sX[tid * kLX] = x0;
+    sX[tid * kLX + 1] = x1;
+  }
+  for (int e = tid; e < kRB * (a.kin - a.din); e += kRowT) {
+    const int r = e / (a.kin - a.din), c = a.din + (e - r * (a.kin - a.din));
+    sX[r * kLX + c] = 0;
+  }
+  for (int e = tid; e < kRB * a.kout; e += kRowT) {
+    const int r = e / a.kout, c = e - r * a.kout;
+    if (c >= a.dout) sD[r * kLD + c] = 0;
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < kRB * a.F; e += kRowT) {
+    const int r = (int)(e / a.F);
+    const int64_t f = e - (int64_t)r * a.F;
+    uint16_t cs = 0, sn = 0;
+    if (spj[r] >= 0) {
+      double s, c;
+      sincos(chirp_phase(sA[r], sB[r], a.tab, a.rows[f]), &s, &c);
+      cs = f2bf((float)c);
+      sn = f2bf((float)(-s));
+    }
+    sX[r * kLX + 2 + 2 * f] = cs;
+    sX[r * kLX + 3 + 2 * f] = sn;
   }
   // biases and targets of this lane's output columns
   float bh[3][kFMaxT], b4v[kFMaxT], tv[kMT][kFMaxT][4];
@@ -864,18 +908,9 @@ __global__ __launch_bounds__(kRowT) void k_mlp_rows(RowArgs a) {
     for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t g = r0 + 16 * mt + rbase + r;
-        tv[mt][j][r] = (oko && g < a.batch) ? a.T[g * a.dout + col] : 0.f;
+        const int64_t pj = spj[16 * mt + rbase + r];
+        tv[mt][j][r] = (oko && pj >= 0) ? a.targets[pj * a.dout + col] : 0.f;
       }
-  }
-#pragma unroll
-  for (int q = 0; q < kXq; ++q) {
-    const int e = tid + kRowT * q, r = e / a.kin, c = e - r * a.kin;
-    if (r < kRB) sX[r * kLX + c] = f2bf(xv[q]);
-  }
-  for (int e = tid; e < kRB * a.kout; e += kRowT) {
-    const int r = e / a.kout, c = e - r * a.kout;
-    if (c >= a.dout) sD[r * kLD + c] = 0;
   }
   __syncthreads();
   f4v acc[kMT][kFMaxT];
@@ -1434,7 +1469,7 @@ int rb_mlp_train(float* p32, uint16_t* p16, float* m, float* v, int din, int hid
   train_carve(ws, batch, din, hidden, dout, &c);
   const Layout L(din, hidden, dout);
   const int64_t n = L.total;
-  const bool fused = fused_ok(din, hidden, dout, p16);
+  const bool fused = rows && fused_ok(din, hidden, dout, p16);
   const int kin = (din + 31) / 32 * 32, kout = (dout + 31) / 32 * 32;
   uint16_t *H[3], *dz[2], *dY, *Xb;
   float *Yw, *part, *splitp, *split1;
@@ -1453,12 +1488,14 @@ int rb_mlp_train(float* p32, uint16_t* p16, float* m, float* v, int din, int hid
   (void)splitk_chunk(batch, &splits);
   for (int64_t s = 0; s < steps; ++s) {
     const int64_t* ix = idx + s * batch;
-    if (rows)
-      RB_HIP(launch_phase_features(params, targets, ix, batch, dout, ranges, rows, F, table, c.X, c.T, stream));
-    else
-      hipLaunchKernelGGL(k_gather, dim3((unsigned)batch), dim3(256), 0, stream, params, targets, ix, batch, dout,
-                         ranges[0], ranges[1], ranges[2], ranges[3], c.X, c.T);
-    RB_HIP(hipGetLastError());
+    if (!fused) {
+      if (rows)
+        RB_HIP(launch_phase_features(params, targets, ix, batch, dout, ranges, rows, F, table, c.X, c.T, stream));
+      else
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)batch), dim3(256), 0, stream, params, targets, ix, batch, dout,
+                           ranges[0], ranges[1], ranges[2], ranges[3], c.X, c.T);
+      RB_HIP(hipGetLastError());
+    }
     const int64_t st = step0 + s + 1;
     const float c1 = 1.f - powf(beta1, (float)st), c2 = 1.f - powf(beta2, (float)st);
     if (!fused) {
@@ -1471,8 +1508,16 @@ int rb_mlp_train(float* p32, uint16_t* p16, float* m, float* v, int din, int hid
       continue;
     }
     RowArgs ra;
-    ra.X = c.X;
-    ra.T = c.T;
+    ra.params = params;
+    ra.targets = targets;
+    ra.idx = ix;
+    ra.rows = rows;
+    ra.tab = table;
+    ra.F = F;
+    ra.mlo = ranges[0];
+    ra.mhi = ranges[1];
+    ra.qlo = ranges[2];
+    ra.qhi = ranges[3];
     ra.batch = batch;
     ra.din = din;
     ra.hid = hidden;
