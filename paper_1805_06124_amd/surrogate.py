@@ -137,24 +137,67 @@ class Surrogate:
     def train(self, params: torch.Tensor, targets: torch.Tensor, steps: int, index_fn, lr0: float = 1e-3,
               log_every: int = 0, log=None) -> list:
         """Adam with cosine-decayed learning rate.  index_fn(start, count)
-        returns a (count, batch) int64 numpy array of sample indices."""
+        returns a (count, batch) int64 numpy array of sample indices.
+
+        The steps run in chunks of 500 (one rb_mlp_train call each).  The
+        host draws the next chunk's indices and reads the previous chunk's
+        losses while the device trains on the current one: indices go up and
+        losses come back through pinned double buffers, so the stream never
+        waits for the host."""
         hist = []
         chunk = 500
-        loss = torch.zeros(chunk, dtype=torch.float32, device=self.dev)
-        s = 0
-        while s < steps:
-            c = min(chunk, steps - s)
-            idx = torch.from_numpy(index_fn(s, c)).to(self.dev)
+        starts = list(range(0, steps, chunk))
+        counts = [min(chunk, steps - s) for s in starts]
+        B = self.batch
+        h_idx = [torch.empty((chunk, B), dtype=torch.int64, pin_memory=True) for _ in range(2)]
+        d_idx = [torch.empty((chunk, B), dtype=torch.int64, device=self.dev) for _ in range(2)]
+        d_loss = [torch.zeros(chunk, dtype=torch.float32, device=self.dev) for _ in range(2)]
+        h_loss = [torch.zeros(chunk, dtype=torch.float32, pin_memory=True) for _ in range(2)]
+        ev_idx = [torch.cuda.Event() for _ in range(2)]
+        ev_loss = [torch.cuda.Event() for _ in range(2)]
+        for e in ev_idx:
+            e.record()
+
+        def logged(i):
+            s = starts[i]
+            return [j for j in range(counts[i]) if log_every and ((s + j) % log_every == 0 or s + j == steps - 1)]
+
+        def fill(i):
+            b = i % 2
+            a = index_fn(starts[i], counts[i])
+            assert a.shape == (counts[i], B), "index_fn must return (count, batch) indices"
+            ev_idx[b].synchronize()  # the upload that last read this buffer has ended
+            h_idx[b].numpy()[:counts[i]] = a
+
+        def drain(i):
+            b = i % 2
+            js = logged(i)
+            if not js:
+                return
+            ev_loss[b].synchronize()
+            lv = h_loss[b].numpy()
+            for j in js:
+                hist.append((starts[i] + j, float(lv[j])))
+                if log:
+                    log("surrogate step %d loss %.3e" % (starts[i] + j, float(lv[j])))
+
+        if starts:
+            fill(0)
+        for i, (s, c) in enumerate(zip(starts, counts)):
+            b = i % 2
+            d_idx[b][:c].copy_(h_idx[b][:c], non_blocking=True)
+            ev_idx[b].record()
             lr = 0.5 * lr0 * (1.0 + np.cos(np.pi * (s + np.arange(c)) / steps))
-            self.train_steps(params, targets, idx, lr, loss)
-            logged = [i for i in range(c) if log_every and ((s + i) % log_every == 0 or s + i == steps - 1)]
-            if logged:
-                lv = loss[:c].cpu().numpy()
-                for i in logged:
-                    hist.append((s + i, float(lv[i])))
-                    if log:
-                        log("surrogate step %d loss %.3e" % (s + i, float(lv[i])))
-            s += c
+            self.train_steps(params, targets, d_idx[b][:c], lr, d_loss[b])
+            if logged(i):
+                h_loss[b][:c].copy_(d_loss[b][:c], non_blocking=True)
+                ev_loss[b].record()
+            if i + 1 < len(starts):
+                fill(i + 1)
+            if i >= 1:
+                drain(i - 1)
+        if starts:
+            drain(len(starts) - 1)
         return hist
 
     def predict(self, params: torch.Tensor, chunk: int = 65536) -> torch.Tensor:

@@ -87,3 +87,29 @@ def test_train_in_chunks_continues_adam(rb):
     torch.cuda.synchronize()
     for name in ("p32", "m", "v", "p16"):
         assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
+def test_pipelined_train_equals_plain_chunks(rb):
+    """Surrogate.train (indices uploaded and losses read back through pinned
+    double buffers while the device trains) gives the same weights and
+    losses as a plain loop of rb_mlp_train calls over the same chunks, with
+    a ragged last chunk."""
+    a, b, params, targets, M = _pair(15, 64, 10, 1000, seed=6)
+    steps, lr0 = 1234, 1e-3
+
+    def index_fn(s0, c):
+        return ri.batch_indices(77, M, 1000, c, s0)
+
+    hist = a.train(params, targets, steps, index_fn, lr0=lr0, log_every=100)
+    ref = []
+    loss = torch.zeros(500, dtype=torch.float32, device="cuda")
+    for s in range(0, steps, 500):
+        c = min(500, steps - s)
+        lr = 0.5 * lr0 * (1.0 + np.cos(np.pi * (s + np.arange(c)) / steps))
+        b.train_steps(params, targets, torch.from_numpy(index_fn(s, c)).cuda(), lr, loss)
+        lv = loss[:c].cpu().numpy()
+        ref += [(s + j, float(lv[j])) for j in range(c) if (s + j) % 100 == 0 or s + j == steps - 1]
+    torch.cuda.synchronize()
+    assert hist == ref
+    for name in ("p32", "m", "v", "p16"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
