@@ -534,7 +534,15 @@ def main():
         gs = rb.greedy(S, tol, w.kmax, W=Wk, ws=wsz, trace=True)
         st = gs["stats"]
         fp64_steps = step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "fp64")
-        ms = st["ms_sweep"] / max(st["sweeps"], 1)
+        # two sweep kernels: k_sweep_look (the sweeps that carried predicted
+        # pivots) and k_sweep_z (the others); the roofline is the one with the
+        # larger share of the run
+        n_look = int(st["look_sweeps"])
+        n_plain = int(st["sweeps"]) - n_look
+        ms_look = st["ms_look_sweep"] / max(n_look, 1)
+        ms_plain = (st["ms_sweep"] - st["ms_look_sweep"]) / max(n_plain, 1)
+        sweep_kernel = "k_sweep_look" if st["ms_look_sweep"] >= st["ms_sweep"] - st["ms_look_sweep"] else "k_sweep_z"
+        ms = ms_look if sweep_kernel == "k_sweep_look" else ms_plain
         by = sweep_bytes(w.N, w.M)
         read_after = achievable_read(rb, S)
         log("plain streaming read of S after the greedy runs: %.1f GB/s" % read_after)
@@ -544,20 +552,28 @@ def main():
                     runs=run_spread(runs),
                     k=int(g["k"]), status=g["status"], err_final=float(g["err"][-1]),
                     anchors=int(g["stats"]["anchors"]), orthogonality=orthogonality(g["E"]),
-                    roofline={"kernel": "k_sweep_z", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+                    roofline={"kernel": sweep_kernel, "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "traffic": measured_traffic("k_sweep_z", w.name),
+                              "traffic": measured_traffic(sweep_kernel, w.name),
                               "ms_per_launch": ms, "bytes_per_launch": by,
                               "achievable_read_GBs": read_gbs,
                               "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read_gbs},
                     breakdown_ms={"sweep": st["ms_sweep"], "fused_sweep_anchor": st["ms_fused"], "gs": st["ms_gs"],
-                                  "anchor": st["ms_anchor"], "total": st["ms_total"]},
-                    sweeps={"plain": int(st["sweeps"]), "fused_with_reanchoring": int(st["fused"])},
+                                  "anchor": st["ms_anchor"], "lookahead_predict": st["ms_look"],
+                                  "lookahead_apply": st["ms_apply"], "total": st["ms_total"]},
+                    sweeps={"all": int(st["sweeps"]), "with_predictions": n_look, "plain": n_plain,
+                            "fused_with_reanchoring": int(st["fused"]),
+                            "steps_from_predictions": int(st["look_steps"]),
+                            "predicted_orthogonalisations": int(st["look_gs"]),
+                            "ms_per_launch": {"k_sweep_look": ms_look if n_look else None,
+                                              "k_sweep_z": ms_plain if n_plain else None}},
                     per_step=fp64_steps, workspace_bytes=int(wsz.numel()))
-        log("fp64 sweep: %.3f ms/launch, %.1f GB/s (%d plain sweeps); %d fused sweep+re-anchoring passes %.1f ms; "
-            "gs %.1f ms, separate anchors %.1f ms (%d anchors in all)" % (
-                ms, fp64["roofline"]["achieved"], st["sweeps"], st["fused"], st["ms_fused"], st["ms_gs"],
+        log("fp64 sweeps: %d with predictions (%.3f ms/launch), %d plain (%.3f ms/launch); %s at %.1f GB/s; "
+            "%d steps from predictions (apply %.1f ms, predictions %.1f ms, %d predicted orthogonalisations); "
+            "%d fused sweep+re-anchoring passes %.1f ms; gs %.1f ms, separate anchors %.1f ms (%d anchors in all)" % (
+                n_look, ms_look, n_plain, ms_plain, sweep_kernel, fp64["roofline"]["achieved"], st["look_steps"],
+                st["ms_apply"], st["ms_look"], st["look_gs"], st["fused"], st["ms_fused"], st["ms_gs"],
                 st["ms_anchor"], st["anchors"]))
         del Wk, gs, runs, wsz
         torch.cuda.empty_cache()

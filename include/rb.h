@@ -117,6 +117,22 @@ typedef struct rb_opts {
                          re-anchoring is accurate enough, fold it into the
                          next sweep (one read of the working matrix for
                          both); 0 = separate passes only.  Default 1. */
+  int32_t lookahead;  /* FP64 greedy: pivots predicted per sweep, 0..4.  Before
+                         a sweep the next pivots are predicted from the
+                         look_k columns with the best estimates: each listed
+                         column's coefficient with the newest vector (and
+                         with each predicted vector in turn) and its updated
+                         Eq. (6.3) estimate are formed with the sweep's own
+                         arithmetic, the best is orthogonalised as its step
+                         would do it, and the sweep reads the working
+                         matrix once for the newest and the predicted
+                         vectors.  A step whose pivot was predicted then
+                         takes that vector and its coefficients without a
+                         sweep of its own.  Pivots, errors, residuals and
+                         basis are bit-identical for every value; columns
+                         of E past the returned k may hold predicted
+                         vectors.  0 = off.  Default 4. */
+  int32_t look_k;     /* length of the candidate list, 1..2048.  Default 512. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */
@@ -139,6 +155,17 @@ typedef struct rb_stats {
                           the working matrix for both; counted in anchors,
                           not in sweeps) */
   double ms_fused;     /* device time of those fused passes */
+  int64_t look_sweeps; /* FP64: sweeps that carried predicted vectors */
+  int64_t look_steps;  /* FP64: steps taken from a prediction (no sweep and
+                          no orthogonalisation of their own; not counted in
+                          sweeps) */
+  int64_t look_gs;     /* FP64: orthogonalisations of predicted pivots */
+  double ms_look;      /* device time of the predictions (candidate list,
+                          reranking, orthogonalisation of predicted pivots) */
+  double ms_apply;     /* device time of the steps taken from a prediction
+                          (estimate update and argmax) */
+  double ms_look_sweep; /* FP64: device time of the sweeps that carried
+                           predicted vectors (part of ms_sweep) */
 } rb_stats;
 
 void rb_default_opts(rb_opts *opts);

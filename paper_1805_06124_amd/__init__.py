@@ -34,14 +34,17 @@ class Opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("nu_max", ctypes.c_int32), ("nu_min", ctypes.c_int32),
                 ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("theta32", ctypes.c_double), ("regen_chunk", ctypes.c_int32), ("certify", ctypes.c_int32),
-                ("step_ms", ctypes.c_void_p), ("fuse", ctypes.c_int32)]
+                ("step_ms", ctypes.c_void_p), ("fuse", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("look_k", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("anchors", ctypes.c_int64), ("gs_passes", ctypes.c_int64),
                 ("ms_sweep", ctypes.c_double), ("ms_gs", ctypes.c_double), ("ms_anchor", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("regen_anchors", ctypes.c_int64), ("misses", ctypes.c_int64),
-                ("fused", ctypes.c_int64), ("ms_fused", ctypes.c_double)]
+                ("fused", ctypes.c_int64), ("ms_fused", ctypes.c_double), ("look_sweeps", ctypes.c_int64),
+                ("look_steps", ctypes.c_int64), ("look_gs", ctypes.c_int64), ("ms_look", ctypes.c_double),
+                ("ms_apply", ctypes.c_double), ("ms_look_sweep", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -62,6 +62,8 @@ void rb_default_opts(rb_opts* o) {
   o->certify = 2;
   o->step_ms = nullptr;
   o->fuse = 1;
+  o->lookahead = 4;
+  o->look_k = 512;
 }
 
 const char* rb_strerror(int status) {
@@ -153,8 +155,11 @@ struct ZScratch {
   ArgMax *part, *res;
   double2 *cpan, *v, *g;
   int* bad;
-  // returns the bytes used (base == nullptr: sizing only)
-  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel) {
+  // pivot lookahead: candidate list and its scratch, list-local sums, rerank partials
+  ArgMax *tk0 = nullptr, *tk1 = nullptr, *list = nullptr, *rpart = nullptr, *lres = nullptr;
+  double* acc_l = nullptr;
+  // returns the bytes used (base == nullptr: sizing only); look_k = 0: no lookahead
+  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel, int look_k) {
     Carve c(base);
     nrm = c.take<double>(M);
     nrm0 = c.take<double>(M);
@@ -167,14 +172,25 @@ struct ZScratch {
     g = c.take<double2>(kcap > 0 ? kcap : 1);
     sq = c.take<double>(4);
     bad = c.take<int>(1);
+    if (look_k > 0) {
+      const int64_t groups = (M + kPivotGroup - 1) / kPivotGroup;
+      tk0 = c.take<ArgMax>(look_list_scratch(groups, look_k));
+      tk1 = c.take<ArgMax>(look_list_scratch(groups, look_k));
+      list = c.take<ArgMax>(look_k);
+      acc_l = c.take<double>(look_k);
+      rpart = c.take<ArgMax>(rerank_partials(look_k));
+      lres = c.take<ArgMax>(1);
+    }
     return c.used;
   }
 };
 
 bool z_opts_ok(const rb_opts& o) {
   return o.kappa > 1.0 && o.nu_max >= 1 && o.nu_min >= 1 && o.nu_min <= o.nu_max && o.theta > 0.0 &&
-         o.theta < 1.0 && o.anchor_max >= 1;
+         o.theta < 1.0 && o.anchor_max >= 1 && o.lookahead >= 0 && o.lookahead <= kLookMax &&
+         (o.lookahead == 0 || (o.look_k >= 1 && o.look_k <= kLookListMax));
 }
+int z_look_k(const rb_opts& o) { return o.lookahead > 0 ? o.look_k : 0; }
 
 }  // namespace
 
@@ -184,7 +200,7 @@ size_t greedy_z_ws_bytes(int64_t N, int64_t M, int64_t kmax, const rb_opts* opts
   if (opts_in) o = *opts_in;
   if (N <= 0 || M <= 0 || kmax < 0 || !z_opts_ok(o)) return 0;
   ZScratch z;
-  return z.carve(nullptr, N, M, std::min(kmax, N), o.anchor_max);
+  return z.carve(nullptr, N, M, std::min(kmax, N), o.anchor_max, z_look_k(o));
 }
 
 // The FP64 greedy, started from k0 >= 0 orthonormal vectors already in
@@ -220,7 +236,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
 
   // scratch: the caller's workspace, or one allocation of the same layout
   ZScratch z;
-  const size_t need = z.carve(nullptr, N, M, std::min(kmax, N), panel);
+  const size_t need = z.carve(nullptr, N, M, std::min(kmax, N), panel, z_look_k(o));
   DevBuf d_ws, d_Wown;
   if (ws) {
     if (ws_bytes < need) {
@@ -232,7 +248,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     RB_ALLOC(d_ws, need);
     ws = d_ws.p;
   }
-  z.carve(ws, N, M, std::min(kmax, N), panel);
+  z.carve(ws, N, M, std::min(kmax, N), panel, z_look_k(o));
   HostWords hw;
   if (hw.init(d_ws.p != nullptr, 96) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
   ArgMax* h_res = hw.at<ArgMax>(0);     // 2 x 16 B
@@ -255,7 +271,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   ArgMax* res = z.res;
   double2* cpan = z.cpan;
   double2* v = z.v;
-  double2* g = z.g;
+  double2* g_coef = z.g;
   double* sq = z.sq;
 
   // ---- initial norms (Alg. 3: sigma_0(s_i) = ||s_i||) ----
@@ -326,6 +342,23 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   }
   err[k] = std::sqrt(A_w > 0.0 ? A_w : 0.0);
 
+  double A_X = A_w;  // largest nrm of X when it was last written
+
+  // Pivot lookahead (rb_look.hip): predictions spec[spec_at .. nspec) made
+  // at the last sweep, each with its vector in E[:, k + d] already and its
+  // coefficients in panel row m + d.  fine_part: part holds the per-group
+  // partials of the current estimates (the list's source).
+  struct Spec {
+    int64_t J;
+    double r;
+    int passes;
+  };
+  Spec spec[kLookMax];
+  int nspec = 0, spec_at = 0;
+  bool fine_part = false;
+  const int look_k = z_look_k(o);
+  const int64_t ngroups = (M + kPivotGroup - 1) / kPivotGroup;
+
   // Re-anchoring against the m panel vectors a..a+m-1 swept since the last
   // writing anchoring.  write: X <- X - E_p C_p (the panel restarts);
   // otherwise only nrm_j <- ||x_j - E_p c_j||^2 (one read of X; the panel
@@ -333,8 +366,9 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   // deflated column by at most u ||x_j|| per vector, an error m u sqrt(A_X)
   // in err that stays far below the rounding of the explicit form).
   // Either way acc <- 0 and the pivot is the argmax of the fresh norms.
-  double A_X = A_w;  // largest nrm of X when it was last written
   auto anchor = [&](bool write, double* slot_ms) -> int {
+    nspec = spec_at = 0;
+    fine_part = false;
     tm.start();
     if (write && !W) {
       const size_t bytes = sizeof(double2) * (size_t)N * (size_t)M;
@@ -386,6 +420,8 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   double est_prev = A_w;
   // the fused pass with the newest vector (column k - 1 of E)
   auto fused_sweep = [&](double* slot_ms, double* est_out, int64_t* J_out) -> int {
+    nspec = spec_at = 0;
+    fine_part = false;
     tm.start();
     RB_HIP(launch_anchor_sweep(X, ldX, N, M, E + a * ldE, ldE, m, cpan, M, E + (k - 1) * ldE, nrm, acc, mask,
                                cpan + m * M, part, np2, res, z.bad, stream));
@@ -403,99 +439,199 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     return RB_OK;
   };
 
+  // Orthogonalisation of column Jc of X against E[:, 0..kk-1] into v
+  // (iterated classical Gram-Schmidt, Hoffmann's kappa criterion); the
+  // caller accepts it (launch_scale_into writes e = v / ||v||) or not.
+  struct Gs {
+    double r, s_norm;
+    int passes;
+    bool settled;  // the last pass met Hoffmann's criterion
+    const double* scale_src;
+  };
+  auto gs_run = [&](int64_t Jc, int64_t kk, Gs& g) -> int {
+    RB_HIP(hipMemcpyAsync(v, X + Jc * ldX, sizeof(double2) * N, hipMemcpyDeviceToDevice, stream));
+    // ||v|| before the first pass: the stored column (its norm differs from
+    // nrm[Jc] after a norms-only re-anchoring)
+    if (kk > 0) {
+      RB_HIP(launch_sqnorms_small(v, N, 1, N, sq + 1, stream));
+      RB_HIP(hipMemcpyAsync(&h_sc[0], sq + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
+    } else {
+      RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + Jc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    RB_HIP(hipMemcpyAsync(&h_sc[1], nrm0 + Jc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    RB_HIP(hipStreamSynchronize(stream));
+    double before = std::sqrt(h_sc[0]);
+    g.s_norm = std::sqrt(h_sc[1]);
+    double after = before;
+    g.scale_src = nrm + Jc;  // kk == 0: the exact column norm
+    g.passes = 0;
+    g.settled = true;
+    if (kk == 0) {
+      g.passes = 1;  // a pass against an empty basis changes nothing
+    } else {
+      g.settled = false;
+      while (g.passes < o.nu_max) {
+        RB_HIP(launch_gemv_ch(E, ldE, kk, v, N, 1, N, g_coef, stream));
+        RB_HIP(launch_gemv_n_sub(E, ldE, kk, g_coef, v, N, 1, N, stream));
+        RB_HIP(launch_sqnorms_small(v, N, 1, N, sq, stream));
+        RB_HIP(hipMemcpyAsync(&h_sc[2], sq, sizeof(double), hipMemcpyDeviceToHost, stream));
+        RB_HIP(hipStreamSynchronize(stream));
+        ++g.passes;
+        after = std::sqrt(h_sc[2]);
+        if (g.passes >= o.nu_min && after > before / o.kappa) {
+          g.settled = true;
+          break;
+        }
+        before = after;
+      }
+      g.scale_src = sq;
+    }
+    g.r = after;
+    return RB_OK;
+  };
+  auto gs_in_span = [&](const Gs& g) { return !(g.r > 64.0 * 0x1p-53 * g.s_norm); };
+
+  // Predict up to dmax next pivots before the sweep with E[:, k-1]: the
+  // best listed column after reranking with E[:, k-1] (then with each
+  // predicted vector in turn), orthogonalised into E[:, k + d] exactly as
+  // its own step would do it.  A prediction whose vector that step would
+  // not accept ends the chain (the step then reports it).
+  auto predict = [&](int dmax, int* nd_out) -> int {
+    *nd_out = 0;
+    tm.start();
+    if (!fine_part) RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
+    RB_HIP(launch_look_list(part, ngroups, look_k, z.tk0, z.tk1, z.list, stream));
+    int64_t ex[kLookMax];
+    int nd = 0;
+    for (int d = 0; d < dmax; ++d) {
+      RB_HIP(launch_rerank(X, N, ldX, E + (k - 1 + d) * ldE, z.list, look_k, nrm, acc, z.acc_l, d == 0 ? 1 : 0,
+                           mask, ex, d, z.rpart, z.lres, stream));
+      RB_HIP(hipMemcpyAsync(h_res + 1, z.lres, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+      RB_HIP(hipStreamSynchronize(stream));
+      const int64_t Jp = h_res[1].i;
+      if (Jp < 0 || std::isnan(h_res[1].v)) break;
+      Gs g;
+      int rc = gs_run(Jp, k + d, g);
+      if (rc != RB_OK) return rc;
+      st.look_gs++;
+      if (!std::isfinite(g.r) || gs_in_span(g) || (!g.settled && g.r >= tol)) break;
+      RB_HIP(launch_scale_into(v, N, g.scale_src, E + (k + d) * ldE, stream));
+      spec[d] = Spec{Jp, g.r, g.passes};
+      ex[d] = Jp;
+      nd = d + 1;
+    }
+    lap(tm, &st.ms_look, nullptr);
+    *nd_out = nd;
+    return RB_OK;
+  };
+
   while (true) {
     if (err[k] < tol) {
       status = RB_OK;
       break;
     }
     if (k == kcap) break;
-    if (J < 0) break;  // every column pivoted
+    if (J < 0) break;
 
-    // ---- 1. orthonormalise x_J (iterated Gram-Schmidt, kappa criterion) ----
-    tm.start();
-    RB_HIP(hipMemcpyAsync(v, X + J * ldX, sizeof(double2) * N, hipMemcpyDeviceToDevice, stream));
-    // ||v|| before the first pass: the stored column (its norm differs from
-    // nrm[J] after a norms-only re-anchoring)
-    if (k > 0) {
-      RB_HIP(launch_sqnorms_small(v, N, 1, N, sq + 1, stream));
-      RB_HIP(hipMemcpyAsync(&h_sc[0], sq + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
-    } else {
-      RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + J, sizeof(double), hipMemcpyDeviceToHost, stream));
-    }
-    RB_HIP(hipMemcpyAsync(&h_sc[1], nrm0 + J, sizeof(double), hipMemcpyDeviceToHost, stream));
-    RB_HIP(hipStreamSynchronize(stream));
-    double before = std::sqrt(h_sc[0]);
-    const double s_norm = std::sqrt(h_sc[1]);
-    double after = before;
-    const double* scale_src = nrm + J;  // k == 0: the exact column norm
-    int passes = 0;
-    bool settled = true;  // the last pass met Hoffmann's criterion
-    if (k == 0) {
-      passes = 1;  // a pass against an empty basis changes nothing
-    } else {
-      settled = false;
-      while (passes < o.nu_max) {
-        RB_HIP(launch_gemv_ch(E, ldE, k, v, N, 1, N, g, stream));
-        RB_HIP(launch_gemv_n_sub(E, ldE, k, g, v, N, 1, N, stream));
-        RB_HIP(launch_sqnorms_small(v, N, 1, N, sq, stream));
-        RB_HIP(hipMemcpyAsync(&h_sc[2], sq, sizeof(double), hipMemcpyDeviceToHost, stream));
-        RB_HIP(hipStreamSynchronize(stream));
-        ++passes;
-        after = std::sqrt(h_sc[2]);
-        if (passes >= o.nu_min && after > before / o.kappa) {
-          settled = true;
-          break;
-        }
-        before = after;
-      }
-      scale_src = sq;
-    }
-    st.gs_passes += passes;
-    const double r = after;
-    lap(tm, &st.ms_gs, slot(k, 0));
-    if (!std::isfinite(r)) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
-    if (!(r > 64.0 * 0x1p-53 * s_norm)) {  // numerically in span(E)
-      status = RB_RANK;
-      break;
-    }
-    if (!settled && r >= tol) {
-      char m2[160];
-      std::snprintf(m2, sizeof m2, "Gram-Schmidt of pivot %lld still shrank ||v|| by kappa after %d passes",
-                    (long long)J, passes);
-      return fail_run(RB_EBREAKDOWN, m2);
-    }
-    tm.start();
-    RB_HIP(launch_scale_into(v, N, scale_src, E + k * ldE, stream));
-    RB_HIP(launch_fill(mask + J, (uint8_t)1, 1, stream));
-    lap(tm, &st.ms_gs, slot(k, 0));
-    piv[k] = J;
-    rho[k] = r;
-    if (nu) nu[k] = passes;
-    ++k;
-
-    // ---- 2. fused sweep with the new vector (panel row m) ----
-    if (m == panel) {
-      int rc = anchor(true, slot(k - 1, 2));
-      if (rc != RB_OK) return rc;
-      // the new vector has not been swept yet: the panel restarts at it
-      a = k - 1;
+    // A step whose pivot was predicted at the last sweep: its vector and its
+    // coefficients are already there, unless this step would not run a
+    // plain sweep (a fused re-anchoring is due).
+    bool taken = false;
+    if (spec_at < nspec) {
+      const bool fused_due = fuse_next && m <= kFuseMaxM && norms_only_ok(est_prev);
+      if (spec[spec_at].J == J && m < panel && !fused_due) taken = true;
+      else nspec = spec_at = 0;
     }
     double est_max = 0.0;
-    if (fuse_next && m <= kFuseMaxM && norms_only_ok(est_prev)) {
-      int rc = fused_sweep(slot(k - 1, 1), &est_max, &J);
-      if (rc != RB_OK) return rc;
-    } else {
+    if (taken) {
+      const Spec sp = spec[spec_at++];
       tm.start();
-      RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr,
-                            stream));
-      lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
+      RB_HIP(launch_fill(mask + J, (uint8_t)1, 1, stream));
+      RB_HIP(launch_est_apply(nrm, acc, mask, cpan + m * M, M, part, np, stream));
       RB_HIP(launch_sweep_final(M, part, res, stream));
       RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
       RB_HIP(hipStreamSynchronize(stream));
-      st.sweeps++;
+      lap(tm, &st.ms_apply, slot(k, 1));
+      piv[k] = J;
+      rho[k] = sp.r;
+      if (nu) nu[k] = sp.passes;
+      st.gs_passes += sp.passes;
+      st.look_steps++;
+      ++k;
       ++m;
+      fine_part = true;
       est_max = h_res->v;
       J = h_res->i;
+    } else {
+      nspec = spec_at = 0;
+      // ---- 1. orthonormalise x_J (iterated Gram-Schmidt, kappa criterion) ----
+      tm.start();
+      Gs g;
+      int rc = gs_run(J, k, g);
+      if (rc != RB_OK) return rc;
+      st.gs_passes += g.passes;
+      lap(tm, &st.ms_gs, slot(k, 0));
+      if (!std::isfinite(g.r)) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
+      if (gs_in_span(g)) {  // numerically in span(E)
+        status = RB_RANK;
+        break;
+      }
+      if (!g.settled && g.r >= tol) {
+        char m2[160];
+        std::snprintf(m2, sizeof m2, "Gram-Schmidt of pivot %lld still shrank ||v|| by kappa after %d passes",
+                      (long long)J, g.passes);
+        return fail_run(RB_EBREAKDOWN, m2);
+      }
+      tm.start();
+      RB_HIP(launch_scale_into(v, N, g.scale_src, E + k * ldE, stream));
+      RB_HIP(launch_fill(mask + J, (uint8_t)1, 1, stream));
+      lap(tm, &st.ms_gs, slot(k, 0));
+      piv[k] = J;
+      rho[k] = g.r;
+      if (nu) nu[k] = g.passes;
+      ++k;
+
+      // ---- 2. sweep with the new vector (panel row m) ----
+      if (m == panel) {
+        rc = anchor(true, slot(k - 1, 2));
+        if (rc != RB_OK) return rc;
+        // the new vector has not been swept yet: the panel restarts at it
+        a = k - 1;
+      }
+      if (fuse_next && m <= kFuseMaxM && norms_only_ok(est_prev)) {
+        rc = fused_sweep(slot(k - 1, 1), &est_max, &J);
+        if (rc != RB_OK) return rc;
+      } else {
+        // predicted vectors ride along in the same read of X, within the
+        // panel and the basis capacity
+        const int64_t dmax = std::min<int64_t>(std::min<int64_t>(o.lookahead, panel - m - 1), kcap - k);
+        int nd = 0;
+        if (dmax > 0) {
+          rc = predict((int)dmax, &nd);
+          if (rc != RB_OK) return rc;
+        }
+        tm.start();
+        if (nd > 0)
+          RB_HIP(launch_sweep_look(X, N, M, ldX, E + (k - 1) * ldE, ldE, 1 + nd, nrm, acc, mask, cpan + m * M, part,
+                                   np, stream));
+        else
+          RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np,
+                                nullptr, stream));
+        const double ms_before = st.ms_sweep;
+        lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
+        if (nd > 0) st.ms_look_sweep += st.ms_sweep - ms_before;
+        RB_HIP(launch_sweep_final(M, part, res, stream));
+        RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+        RB_HIP(hipStreamSynchronize(stream));
+        st.sweeps++;
+        if (nd > 0) st.look_sweeps++;
+        ++m;
+        fine_part = true;
+        nspec = nd;
+        spec_at = 0;
+        est_max = h_res->v;
+        J = h_res->i;
+      }
     }
     if (J >= 0 && std::isnan(est_max)) return fail_run(RB_ENONFINITE, "a swept estimate is not finite");
 

@@ -57,6 +57,23 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// The pivot search's coefficient arithmetic, shared by every kernel that
+// forms c = e^H x for it: each lane accumulates conj(e_n) x_n over its rows
+// n = lane, lane + 64, lane + 128, ... in increasing order with explicit
+// fused multiply-adds, then wave_sum adds the 64 lane sums.  Any two kernels
+// that keep this order produce the same bits for the same (e, x), whatever
+// their unrolling or how many columns and vectors a wave carries.
+__device__ __forceinline__ void sweep_cmac(const double2 e, const double2 s, double& re, double& im) {
+  re = __builtin_fma(e.y, s.y, __builtin_fma(e.x, s.x, re));
+  im = __builtin_fma(-e.y, s.x, __builtin_fma(e.x, s.y, im));
+}
+// acc + |c|^2, rounded the same way wherever the running sum of Eq. (6.3)
+// is advanced
+__device__ __forceinline__ double sweep_acc_add(double a, double cr, double ci) {
+#pragma clang fp contract(off)
+  return a + __builtin_fma(cr, cr, ci * ci);
+}
+
 // Error-free transformations (Knuth two-sum; fma product) for the exact
 // squared norms.  Contraction is switched off in each of them: fusing the
 // product v*v into the following sum would break the two-sum identity.
@@ -156,6 +173,38 @@ hipError_t launch_sweep_final(int64_t M, const ArgMax* partial, ArgMax* result, 
 hipError_t launch_est_argmax(const double* nrm, const double* acc, const uint8_t* mask, int64_t M,
                              ArgMax* partial, int64_t npartial_cap, ArgMax* result, hipStream_t s);
 int64_t sweep_partials_needed(int64_t M);
+// the final reduction alone, over n partial records
+hipError_t launch_argmax_records(const ArgMax* partial, int64_t n, ArgMax* result, hipStream_t s);
+
+// Pivot lookahead of the FP64 greedy (rb_look.hip).  The sweep kernels keep
+// one partial argmax per kPivotGroup consecutive columns.
+//   launch_sweep_look: the sweep with V = 1 + d vectors E[:, 0..V-1] (d <=
+//     kLookMax predicted ones): vector 0 advances acc and gives the per-group
+//     partials (reduce with launch_sweep_final), vector v's coefficients go
+//     to c_out[v * M + j];
+//   launch_est_apply: acc_j += |c_j|^2 from stored coefficients (c == NULL:
+//     none) and the per-group partials of nrm - acc;
+//   launch_look_list: the best K of n partial records (K <= kLookListMax),
+//     through two scratch buffers of look_list_scratch(n, K) records;
+//   launch_rerank: for the K listed columns, c = e^H x_q and a = acc + |c|^2
+//     (acc_g[q] when first, else acc_l[slot]; a -> acc_l[slot]) and the argmax
+//     of nrm_q - a over listed columns neither masked nor in excl[0..nexcl);
+//     partial holds rerank_partials(K) records.
+constexpr int kPivotGroup = 16;
+constexpr int kLookMax = 4;
+constexpr int kLookListMax = 2048;
+hipError_t launch_sweep_look(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* E, int64_t ldE,
+                             int V, const double* nrm, double* acc, const uint8_t* mask, double2* c_out,
+                             ArgMax* partial, int64_t npartial_cap, hipStream_t s);
+hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask, const double2* c, int64_t M,
+                            ArgMax* partial, int64_t npartial_cap, hipStream_t s);
+int64_t look_list_scratch(int64_t n, int K);
+hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* tmp0, ArgMax* tmp1, ArgMax* list,
+                            hipStream_t s);
+int64_t rerank_partials(int K);
+hipError_t launch_rerank(const double2* X, int64_t N, int64_t ldX, const double2* e, const ArgMax* list, int K,
+                         const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
+                         const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* result, hipStream_t s);
 
 // mixed precision: complex64 sweep with FP32 basis copy -> kTop best
 // (est, index) in top[0..kTop) (descending, ties to the lower index)

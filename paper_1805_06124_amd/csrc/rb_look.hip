@@ -1,0 +1,340 @@
+// Pivot lookahead for the FP64 greedy (Alg. 3, Sec. 6.1.2): one read of the
+// working columns serves several greedy steps when the next pivots can be
+// named before the read.
+//
+// At a sweep with the newest basis vector e_0 the host predicts the next
+// pivots from a short list of columns (the best estimates before the
+// sweep): for each listed column it forms the coefficients and the Eq. (6.3)
+// estimates that the coming sweeps would give it (k_rerank), takes the
+// largest, orthogonalises that column as the next step would (e_1), and so
+// on for e_2, e_3, ...  The sweep then reads X once for all of them
+// (k_sweep_look): e_0's coefficients advance the estimates and give the true
+// next pivot; the others are only stored.  When the true pivot is the
+// predicted one, the next step takes e_1 and its stored coefficients
+// (k_est_apply) instead of orthogonalising and sweeping again.
+//
+// Every coefficient and estimate here is formed with the plain sweep's
+// arithmetic (sweep_cmac over rows in increasing order per lane, wave_sum,
+// sweep_acc_add), and the predicted vectors are orthogonalised by the same
+// code as a regular step, so a greedy with lookahead returns the same bits
+// as one without: a wrong prediction costs time, never accuracy.
+#include "rb_internal.h"
+
+namespace rb {
+
+namespace {
+
+constexpr int kLookWaves = 4;
+constexpr int kLookCols = 4;    // columns per wave
+constexpr int kLookUnroll = 2;  // 64-row blocks in flight per column
+static_assert(kLookWaves * kLookCols == kPivotGroup, "one partial argmax per pivot group");
+
+// c_v(j) = e_v^H x_j for the V vectors E[:, 0..V-1] and every column j.
+// Vector 0 advances the running sums (acc_j += |c_0(j)|^2) and gives the
+// masked argmax of est_j = nrm_j - acc_j per workgroup; the coefficients of
+// vector v go to c_out[v * M + j].
+template <int V>
+__global__ __launch_bounds__(kLookWaves * 64) void k_sweep_look(
+    const double2* __restrict__ S, int64_t N, int64_t M, int64_t ldS, const double2* __restrict__ E, int64_t ldE,
+    const double* __restrict__ nrm, double* __restrict__ acc, const uint8_t* __restrict__ mask,
+    double2* __restrict__ c_out, ArgMax* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t col0 = (int64_t)blockIdx.x * kPivotGroup + (int64_t)wave * kLookCols;
+  // columns past M read the last column (results discarded)
+  const double2* cp[kLookCols];
+#pragma unroll
+  for (int c = 0; c < kLookCols; ++c) {
+    int64_t j = col0 + c;
+    if (j > M - 1) j = M - 1;
+    cp[c] = S + j * ldS;
+  }
+  double re[V][kLookCols], im[V][kLookCols];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int c = 0; c < kLookCols; ++c) re[v][c] = im[v][c] = 0.0;
+
+  constexpr int kStep = 64 * kLookUnroll;
+  const int64_t nfull = (N / kStep) * kStep;
+  for (int64_t base = 0; base < nfull; base += kStep) {
+    double2 ev[V][kLookUnroll];
+    double2 sv[kLookCols][kLookUnroll];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int u = 0; u < kLookUnroll; ++u) ev[v][u] = E[v * ldE + base + 64 * u + lane];
+#pragma unroll
+    for (int c = 0; c < kLookCols; ++c)
+#pragma unroll
+      for (int u = 0; u < kLookUnroll; ++u) sv[c][u] = ld_stream(cp[c] + base + 64 * u + lane);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int c = 0; c < kLookCols; ++c)
+#pragma unroll
+        for (int u = 0; u < kLookUnroll; ++u) sweep_cmac(ev[v][u], sv[c][u], re[v][c], im[v][c]);
+  }
+  for (int64_t n = nfull + lane; n < N; n += 64) {
+    double2 sv[kLookCols];
+#pragma unroll
+    for (int c = 0; c < kLookCols; ++c) sv[c] = ld_stream(cp[c] + n);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double2 e = E[v * ldE + n];
+#pragma unroll
+      for (int c = 0; c < kLookCols; ++c) sweep_cmac(e, sv[c], re[v][c], im[v][c]);
+    }
+  }
+
+  vi best = {0.0, -1};
+#pragma unroll
+  for (int c = 0; c < kLookCols; ++c) {
+    const int64_t j = col0 + c;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double cr = wave_sum(re[v][c]);
+      const double ci = wave_sum(im[v][c]);
+      // lane c + 4 v stores (spreads the epilogue over lanes)
+      if (j < M && lane == c + kLookCols * v) {
+        if (v == 0) {
+          const double a = sweep_acc_add(acc[j], cr, ci);
+          acc[j] = a;
+          c_out[j] = make_double2(cr, ci);
+          if (!(mask && mask[j])) best = vi_max(best, vi{nrm[j] - a, j});
+        } else {
+          c_out[v * M + j] = make_double2(cr, ci);
+        }
+      }
+    }
+  }
+  best = wave_vi_max(best);
+  __shared__ vi sbest[kLookWaves];
+  if (lane == 0) sbest[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    vi b = sbest[0];
+#pragma unroll
+    for (int w = 1; w < kLookWaves; ++w) b = vi_max(b, sbest[w]);
+    partial[blockIdx.x].v = b.v;
+    partial[blockIdx.x].i = b.i;
+  }
+}
+
+// A step taken from a lookahead: acc_j += |c_j|^2 with the stored
+// coefficients (c == NULL: acc unchanged), and the masked argmax of
+// nrm_j - acc_j per group of kPivotGroup columns, the sweep's layout.
+__global__ __launch_bounds__(256) void k_est_apply(const double* __restrict__ nrm, double* __restrict__ acc,
+                                                   const uint8_t* __restrict__ mask, const double2* __restrict__ c,
+                                                   int64_t M, ArgMax* __restrict__ partial) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  vi best = {0.0, -1};
+  if (j < M) {
+    double a = acc[j];
+    if (c) {
+      const double2 cj = c[j];
+      a = sweep_acc_add(a, cj.x, cj.y);
+      acc[j] = a;
+    }
+    if (!(mask && mask[j])) best = vi{nrm[j] - a, j};
+  }
+#pragma unroll
+  for (int o = 1; o < kPivotGroup; o <<= 1) {
+    vi y;
+    y.v = __shfl_xor(best.v, o, kWave);
+    y.i = __shfl_xor(best.i, o, kWave);
+    best = vi_max(best, y);
+  }
+  if ((threadIdx.x % kPivotGroup) == 0 && j < M) {
+    partial[j / kPivotGroup].v = best.v;
+    partial[j / kPivotGroup].i = best.i;
+  }
+}
+
+// Bitonic sort of up to kTopN records per workgroup, best first (the vi
+// order: larger value, NaN above numbers, ties to the lower index, records
+// with index < 0 last); the first K go to out[blockIdx.x * K ...].
+constexpr int kTopN = 4096;
+constexpr int kTopThreads = 1024;
+__device__ __forceinline__ bool ranks_above(double av, int64_t ai, double bv, int64_t bi) {
+  if (ai < 0) return false;
+  if (bi < 0) return true;
+  const bool an = av != av, bn = bv != bv;
+  if (an != bn) return an;
+  if (!an && av != bv) return av > bv;
+  return ai < bi;
+}
+__global__ __launch_bounds__(kTopThreads) void k_topk(const ArgMax* __restrict__ in, int64_t n, int K,
+                                                       ArgMax* __restrict__ out) {
+  __shared__ double sv[kTopN];
+  __shared__ int64_t si[kTopN];
+  const int64_t base = (int64_t)blockIdx.x * kTopN;
+  for (int t = threadIdx.x; t < kTopN; t += kTopThreads) {
+    const int64_t g = base + t;
+    if (g < n) {
+      sv[t] = in[g].v;
+      si[t] = in[g].i;
+    } else {
+      sv[t] = 0.0;
+      si[t] = -1;
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= kTopN; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < kTopN / 2; t += kTopThreads) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool best_first = (lo & size) == 0;
+        const bool swap = ranks_above(sv[hi], si[hi], sv[lo], si[lo]) == best_first;
+        if (swap) {
+          const double tv = sv[lo];
+          const int64_t ti = si[lo];
+          sv[lo] = sv[hi];
+          si[lo] = si[hi];
+          sv[hi] = tv;
+          si[hi] = ti;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = threadIdx.x; r < K; r += kTopThreads) {
+    out[(int64_t)blockIdx.x * K + r].v = sv[r];
+    out[(int64_t)blockIdx.x * K + r].i = si[r];
+  }
+}
+
+// One wave per listed column q: c = e^H x_q (the sweep's order), a = acc + |c|^2
+// (acc from acc_g[q] when first, else this column's slot of acc_l; a goes to
+// acc_l), and the workgroup's argmax of nrm_q - a over listed columns that are
+// neither masked nor among the nex excluded ones.
+struct Excl {
+  int64_t j[kLookMax];
+  int n;
+};
+constexpr int kRerankWaves = 4;
+constexpr int kRerankUnroll = 4;
+__global__ __launch_bounds__(kRerankWaves * 64) void k_rerank(
+    const double2* __restrict__ X, int64_t N, int64_t ldX, const double2* __restrict__ e,
+    const ArgMax* __restrict__ list, int K, const double* __restrict__ nrm, const double* __restrict__ acc_g,
+    double* __restrict__ acc_l, int first, const uint8_t* __restrict__ mask, Excl ex, ArgMax* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * kRerankWaves + wave;
+  vi best = {0.0, -1};
+  const int64_t q = slot < K ? list[slot].i : -1;
+  if (q >= 0) {
+    const double2* x = X + q * ldX;
+    double re = 0.0, im = 0.0;
+    for (int64_t n0 = lane; n0 < N; n0 += 64 * kRerankUnroll) {
+      double2 xv[kRerankUnroll], ev[kRerankUnroll];
+#pragma unroll
+      for (int u = 0; u < kRerankUnroll; ++u) {
+        const int64_t n = n0 + 64 * u;
+        xv[u] = n < N ? ld_stream(x + n) : make_double2(0.0, 0.0);
+        ev[u] = n < N ? e[n] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < kRerankUnroll; ++u)
+        if (n0 + 64 * u < N) sweep_cmac(ev[u], xv[u], re, im);
+    }
+    const double cr = wave_sum(re);
+    const double ci = wave_sum(im);
+    const double a = sweep_acc_add(first ? acc_g[q] : acc_l[slot], cr, ci);
+    if (lane == 0) acc_l[slot] = a;
+    bool skip = mask && mask[q];
+    for (int t = 0; t < ex.n; ++t) skip = skip || (ex.j[t] == q);
+    if (!skip) best = vi{nrm[q] - a, q};
+  }
+  // every lane of a wave holds the same record
+  __shared__ vi sbest[kRerankWaves];
+  if (lane == 0) sbest[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    vi b = sbest[0];
+#pragma unroll
+    for (int w = 1; w < kRerankWaves; ++w) b = vi_max(b, sbest[w]);
+    partial[blockIdx.x].v = b.v;
+    partial[blockIdx.x].i = b.i;
+  }
+}
+
+template <int V>
+hipError_t launch_sweep_look_t(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* E, int64_t ldE,
+                               const double* nrm, double* acc, const uint8_t* mask, double2* c_out,
+                               ArgMax* partial, hipStream_t s) {
+  const int64_t grid = (M + kPivotGroup - 1) / kPivotGroup;
+  hipLaunchKernelGGL(k_sweep_look<V>, dim3((unsigned)grid), dim3(kLookWaves * 64), 0, s, S, N, M, ldS, E, ldE, nrm,
+                     acc, mask, c_out, partial);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep_look(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* E, int64_t ldE,
+                             int V, const double* nrm, double* acc, const uint8_t* mask, double2* c_out,
+                             ArgMax* partial, int64_t npartial_cap, hipStream_t s) {
+  if ((M + kPivotGroup - 1) / kPivotGroup > npartial_cap || (M + kPivotGroup - 1) / kPivotGroup > 0x7fffffff)
+    return hipErrorInvalidValue;
+  switch (V) {
+    case 2: return launch_sweep_look_t<2>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
+    case 3: return launch_sweep_look_t<3>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
+    case 4: return launch_sweep_look_t<4>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
+    case 5: return launch_sweep_look_t<5>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask, const double2* c, int64_t M,
+                            ArgMax* partial, int64_t npartial_cap, hipStream_t s) {
+  if ((M + kPivotGroup - 1) / kPivotGroup > npartial_cap) return hipErrorInvalidValue;
+  const int64_t grid = (M + 255) / 256;
+  hipLaunchKernelGGL(k_est_apply, dim3((unsigned)grid), dim3(256), 0, s, nrm, acc, mask, c, M, partial);
+  return hipGetLastError();
+}
+
+int64_t look_list_scratch(int64_t n, int K) {
+  const int64_t first = (n + kTopN - 1) / kTopN * K;
+  return first > K ? first : K;
+}
+
+hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* tmp0, ArgMax* tmp1, ArgMax* list,
+                            hipStream_t s) {
+  if (K < 1 || K > kLookListMax) return hipErrorInvalidValue;
+  const ArgMax* src = partial;
+  ArgMax* bufs[2] = {tmp0, tmp1};
+  int which = 0;
+  // each level keeps the best K of every kTopN records (K <= kTopN / 2, so
+  // the count at least halves per level)
+  while (n > kTopN) {
+    const int64_t blocks = (n + kTopN - 1) / kTopN;
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)blocks), dim3(kTopThreads), 0, s, src, n, K, bufs[which]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = bufs[which];
+    which ^= 1;
+    n = blocks * K;
+  }
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(kTopThreads), 0, s, src, n, K, list);
+  return hipGetLastError();
+}
+
+int64_t rerank_partials(int K) { return (K + kRerankWaves - 1) / kRerankWaves; }
+
+hipError_t launch_rerank(const double2* X, int64_t N, int64_t ldX, const double2* e, const ArgMax* list, int K,
+                         const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
+                         const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* result, hipStream_t s) {
+  if (K < 1 || nexcl < 0 || nexcl > kLookMax) return hipErrorInvalidValue;
+  Excl ex;
+  ex.n = nexcl;
+  for (int t = 0; t < kLookMax; ++t) ex.j[t] = t < nexcl ? excl[t] : -1;
+  const int64_t grid = rerank_partials(K);
+  hipLaunchKernelGGL(k_rerank, dim3((unsigned)grid), dim3(kRerankWaves * 64), 0, s, X, N, ldX, e, list, K, nrm,
+                     acc_g, acc_l, first, mask, ex, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_argmax_records(partial, grid, result, s);
+}
+
+}  // namespace rb

@@ -18,12 +18,8 @@ constexpr int kSweepWaves = 4;     // waves per workgroup
 constexpr int kSweepCols = 4;      // columns per wave
 constexpr int kSweepUnroll = 4;    // 64-row blocks in flight per column
 constexpr int kColsPerBlock = kSweepWaves * kSweepCols;
+static_assert(kColsPerBlock == kPivotGroup, "one partial argmax per pivot group");
 
-__device__ __forceinline__ void cmac_conj(const double2 e, const double2 s, double& re, double& im) {
-  // conj(e) * s
-  re += e.x * s.x + e.y * s.y;
-  im += e.x * s.y - e.y * s.x;
-}
 
 // --------------------------------------------------------------------------
 // Exact squared column norms.  One wave per column; every lane accumulates a
@@ -94,13 +90,13 @@ __global__ __launch_bounds__(kSweepWaves * 64) void k_sweep_z(
 #pragma unroll
     for (int c = 0; c < kSweepCols; ++c)
 #pragma unroll
-      for (int u = 0; u < kSweepUnroll; ++u) cmac_conj(ev[u], sv[c][u], re[c], im[c]);
+      for (int u = 0; u < kSweepUnroll; ++u) sweep_cmac(ev[u], sv[c][u], re[c], im[c]);
   }
   // ragged tail (N not a multiple of 64 * kSweepUnroll)
   for (int64_t n = nfull + lane; n < N; n += 64) {
     double2 ev = e[n];
 #pragma unroll
-    for (int c = 0; c < kSweepCols; ++c) cmac_conj(ev, ld_stream(cp[c] + n), re[c], im[c]);
+    for (int c = 0; c < kSweepCols; ++c) sweep_cmac(ev, ld_stream(cp[c] + n), re[c], im[c]);
   }
 
   vi best = {0.0, -1};
@@ -112,7 +108,7 @@ __global__ __launch_bounds__(kSweepWaves * 64) void k_sweep_z(
     if (j < M) {
       // lane c finishes column c (spreads the epilogue's loads over lanes)
       if (lane == c) {
-        double a = acc[j] + (cr * cr + ci * ci);
+        double a = sweep_acc_add(acc[j], cr, ci);
         acc[j] = a;
         if (kStoreC) c_out[j * ldc] = make_double2(cr, ci);
         if (!(mask && mask[j])) {
@@ -242,6 +238,11 @@ hipError_t launch_sweep_z(const double2* S, int64_t N, int64_t M, int64_t ldS, c
 hipError_t launch_sweep_final(int64_t M, const ArgMax* partial, ArgMax* result, hipStream_t s) {
   const int64_t grid = (M + kColsPerBlock - 1) / kColsPerBlock;
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, s, partial, grid, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmax_records(const ArgMax* partial, int64_t n, ArgMax* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, s, partial, n, result);
   return hipGetLastError();
 }
 

@@ -133,12 +133,16 @@ def test_step_trace(rb):
     g = rb.greedy(S, w.tol, w.kmax, trace=True)
     t, st = g["step_ms"], g["stats"]
     assert t.shape == (g["k"] + 1, 3) and np.all(t >= 0)
-    # the sweep slot holds a plain sweep or a fused pass (re-anchoring and sweep)
-    sweep_ms = st["ms_sweep"] + st["ms_fused"]
+    # the sweep slot holds a plain sweep, a fused pass (re-anchoring and
+    # sweep) or the estimate update of a step taken from a prediction
+    sweep_ms = st["ms_sweep"] + st["ms_fused"] + st["ms_apply"]
     assert abs(t[:, 1].sum() - sweep_ms) <= 1e-6 * sweep_ms + 1e-9
     assert abs(t[:, 0].sum() - st["ms_gs"]) <= 1e-6 * st["ms_gs"] + 1e-9
     assert t[:, 2].sum() <= st["ms_anchor"] + 1e-9  # the initial norms are not a step's
-    assert np.count_nonzero(t[:, 1]) == st["sweeps"] + st["fused"] == g["k"]
+    assert np.count_nonzero(t[:, 1]) == st["sweeps"] + st["fused"] + st["look_steps"] == g["k"]
+    # a step taken from a prediction has no orthogonalisation of its own
+    assert np.count_nonzero(t[:, 0]) == g["k"] - st["look_steps"]
+    assert st["ms_look"] > 0 and st["look_gs"] >= st["look_steps"]
     P = _dev(w.params())
     S32 = rb.chirp_fill(P, w.N, w.flo, w.fhi, dtype=torch.complex64)
     gc = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, trace=True)

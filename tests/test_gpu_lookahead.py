@@ -1,0 +1,99 @@
+"""Pivot lookahead of the FP64 greedy: a sweep that also carries predicted
+vectors, and steps taken from those predictions without a sweep of their
+own, must leave every output bit-identical to the greedy without lookahead
+(the predicted coefficients and estimates are formed with the sweep's own
+arithmetic and the predicted vectors by the same orthogonalisation code).
+
+Cases: the small chirp workload at every depth, short candidate lists
+(many wrong predictions), a narrow coefficient panel (predictions cut at
+the panel's end, written re-anchorings), a continuation from a given basis,
+Gaussian columns, and Kahan's matrix stopped by the breakdown test."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rb_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _same(g0, g1):
+    assert g0["k"] == g1["k"] and g0["status"] == g1["status"]
+    for key in ("piv", "err", "rho", "nu"):
+        np.testing.assert_array_equal(g0[key], g1[key], err_msg=key)
+    assert torch.equal(g0["E"], g1["E"])
+
+
+@pytest.fixture(scope="module")
+def chirp_small():
+    w = ri.WORKLOADS["chirp_small_c128"]
+    return w, _dev(oracle.chirp(w.params(), w.N, w.flo, w.fhi))
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+def test_lookahead_bit_identical(rb, chirp_small, depth):
+    w, S = chirp_small
+    g0 = rb.greedy(S, w.tol, w.kmax, lookahead=0)
+    g1 = rb.greedy(S, w.tol, w.kmax, lookahead=depth)
+    _same(g0, g1)
+    st = g1["stats"]
+    assert g0["stats"]["look_steps"] == 0 and g0["stats"]["look_gs"] == 0
+    assert st["look_steps"] > 0 and st["look_sweeps"] > 0
+    # every basis vector has exactly one sweep, fused pass or prediction
+    assert st["sweeps"] + st["fused"] + st["look_steps"] == g1["k"]
+    assert st["look_steps"] <= depth * st["look_sweeps"]
+
+
+@pytest.mark.parametrize("look_k", [1, 3, 2048])
+def test_lookahead_list_lengths(rb, chirp_small, look_k):
+    w, S = chirp_small
+    g0 = rb.greedy(S, w.tol, w.kmax, lookahead=0)
+    g1 = rb.greedy(S, w.tol, w.kmax, lookahead=4, look_k=look_k)
+    _same(g0, g1)
+
+
+def test_lookahead_narrow_panel_and_theta(rb, chirp_small):
+    """anchor_max = 6: predictions stop at the panel's end and written
+    re-anchorings come every few steps; theta = 1e-3 adds norms-only and
+    fused re-anchorings."""
+    w, S = chirp_small
+    for kw in (dict(anchor_max=6), dict(theta=1e-3), dict(anchor_max=6, theta=1e-3, fuse=0)):
+        g0 = rb.greedy(S, w.tol, w.kmax, W=torch.empty_like(S), lookahead=0, **kw)
+        g1 = rb.greedy(S, w.tol, w.kmax, W=torch.empty_like(S), lookahead=4, **kw)
+        _same(g0, g1)
+        assert g1["stats"]["anchors"] == g0["stats"]["anchors"]
+
+
+def test_lookahead_resume(rb):
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S = _dev(oracle.chirp(w.params(M=900), 700, w.flo, w.fhi))
+    E0 = rb.greedy(S, w.tol, w.kmax)["E"][:12].contiguous()
+    g0 = rb.greedy(S, w.tol, w.kmax, E0=E0, W=torch.empty_like(S), lookahead=0)
+    g1 = rb.greedy(S, w.tol, w.kmax, E0=E0, W=torch.empty_like(S), lookahead=3)
+    _same(g0, g1)
+    assert g1["stats"]["look_steps"] > 0
+
+
+def test_lookahead_gaussian_and_kmax(rb):
+    """Gaussian columns (flat spectrum: many wrong predictions) up to kmax,
+    with kmax cutting a prediction chain."""
+    S = _dev(ri.gaussian(3, 500, 700))
+    for kmax in (37, 120):
+        g0 = rb.greedy(S, 0.0, kmax, lookahead=0)
+        g1 = rb.greedy(S, 0.0, kmax, lookahead=4)
+        _same(g0, g1)
+        assert g1["k"] == kmax
+
+
+def test_lookahead_breakdown(rb):
+    theta, delta, n = 1.3, 1e-3, 80
+    S = _dev(ri.kahan(n, theta, delta))
+    g0 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=0)
+    g1 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=4)
+    assert g1["status"] == "EBREAKDOWN"
+    _same(g0, g1)
