@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kLookWaves = 4;
 constexpr int kLookCols = 4;    // columns per wave
-constexpr int kLookUnroll = 2;  // 64-row blocks in flight per column
+constexpr int kLookUnroll = 3;  // 64-row blocks in flight per column
 static_assert(kLookWaves * kLookCols == kPivotGroup, "one partial argmax per pivot group");
 
 // c_v(j) = e_v^H x_j for the V vectors E[:, 0..V-1] and every column j.
