@@ -75,6 +75,12 @@ def sweep_bytes(N, M):
     return 16 * N * M + 16 * N + (8 + 16 + 1 + 16) * M
 
 
+def look_sweep_bytes(N, M, V):
+    # as sweep_bytes with V vectors read (16 N each) and V coefficient rows
+    # written (16 M each); V may be the mean over the launches
+    return 16 * N * M + 16 * N * V + (8 + 16 + 1 + 16 * V) * M
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -175,8 +181,9 @@ def surrogate_leg(rb, ri, w, E, C, params, args, log):
 def pmc_probe(rb, w, params, log):
     """Kernels for the HBM byte counters: one plain device-to-device copy of
     4 GiB (known traffic: 4 GiB read, 4 GiB written) to calibrate the
-    counters, then three fused sweeps of the workload in complex128 and
-    three in complex64."""
+    counters, then three fused sweeps of the workload in complex128, the
+    first 12 greedy steps (sweeps with predicted vectors), and three sweeps
+    in complex64."""
     import torch
     n = (4 << 30) // 16
     src = torch.ones(n, dtype=torch.complex128, device=params.device)
@@ -193,7 +200,12 @@ def pmc_probe(rb, w, params, log):
     for i in range(3):
         est, J = rb.sweep(S, e, nrm, acc, None, c)
         log("sweep %d: J=%d est=%.6f bytes=%d" % (i, J, est, sweep_bytes(w.N, w.M)))
-    del S
+    # the first 12 steps of the greedy: sweeps that carry predicted vectors
+    g = rb.greedy(S, 0.0, 12, collect_stats=1)
+    st = g["stats"]
+    log("greedy, 12 steps: %d sweeps with predictions carrying %d vectors, %d plain" % (
+        st["look_sweeps"], st["look_vectors"], st["sweeps"] - st["look_sweeps"]))
+    del S, g
     S32 = rb.chirp_fill(params, w.N, w.flo, w.fhi, dtype=torch.complex64)
     e32 = S32[0].contiguous()
     acc.zero_()
@@ -543,7 +555,8 @@ def main():
         ms_plain = (st["ms_sweep"] - st["ms_look_sweep"]) / max(n_plain, 1)
         sweep_kernel = "k_sweep_look" if st["ms_look_sweep"] >= st["ms_sweep"] - st["ms_look_sweep"] else "k_sweep_z"
         ms = ms_look if sweep_kernel == "k_sweep_look" else ms_plain
-        by = sweep_bytes(w.N, w.M)
+        v_mean = 1.0 + st["look_vectors"] / max(n_look, 1)
+        by = look_sweep_bytes(w.N, w.M, v_mean) if sweep_kernel == "k_sweep_look" else sweep_bytes(w.N, w.M)
         read_after = achievable_read(rb, S)
         log("plain streaming read of S after the greedy runs: %.1f GB/s" % read_after)
         read_gbs = max(read_gbs, read_after)
@@ -566,6 +579,7 @@ def main():
                             "fused_with_reanchoring": int(st["fused"]),
                             "steps_from_predictions": int(st["look_steps"]),
                             "predicted_orthogonalisations": int(st["look_gs"]),
+                            "vectors_per_predicting_sweep": v_mean,
                             "ms_per_launch": {"k_sweep_look": ms_look if n_look else None,
                                               "k_sweep_z": ms_plain if n_plain else None}},
                     per_step=fp64_steps, workspace_bytes=int(wsz.numel()))

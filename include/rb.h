@@ -166,6 +166,7 @@ typedef struct rb_stats {
                           (estimate update and argmax) */
   double ms_look_sweep; /* FP64: device time of the sweeps that carried
                            predicted vectors (part of ms_sweep) */
+  int64_t look_vectors; /* FP64: predicted vectors carried by those sweeps */
 } rb_stats;
 
 void rb_default_opts(rb_opts *opts);

@@ -44,7 +44,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("regen_anchors", ctypes.c_int64), ("misses", ctypes.c_int64),
                 ("fused", ctypes.c_int64), ("ms_fused", ctypes.c_double), ("look_sweeps", ctypes.c_int64),
                 ("look_steps", ctypes.c_int64), ("look_gs", ctypes.c_int64), ("ms_look", ctypes.c_double),
-                ("ms_apply", ctypes.c_double), ("ms_look_sweep", ctypes.c_double)]
+                ("ms_apply", ctypes.c_double), ("ms_look_sweep", ctypes.c_double),
+                ("look_vectors", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

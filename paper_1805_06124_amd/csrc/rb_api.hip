@@ -156,7 +156,7 @@ struct ZScratch {
   double2 *cpan, *v, *g;
   int* bad;
   // pivot lookahead: candidate list and its scratch, list-local sums, rerank partials
-  ArgMax *tk0 = nullptr, *tk1 = nullptr, *list = nullptr, *rpart = nullptr, *lres = nullptr;
+  ArgMax *list = nullptr, *rpart = nullptr, *lres = nullptr;
   double* acc_l = nullptr;
   // returns the bytes used (base == nullptr: sizing only); look_k = 0: no lookahead
   size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel, int look_k) {
@@ -173,9 +173,6 @@ struct ZScratch {
     sq = c.take<double>(4);
     bad = c.take<int>(1);
     if (look_k > 0) {
-      const int64_t groups = (M + kPivotGroup - 1) / kPivotGroup;
-      tk0 = c.take<ArgMax>(look_list_scratch(groups, look_k));
-      tk1 = c.take<ArgMax>(look_list_scratch(groups, look_k));
       list = c.take<ArgMax>(look_k);
       acc_l = c.take<double>(look_k);
       rpart = c.take<ArgMax>(rerank_partials(look_k));
@@ -500,7 +497,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     *nd_out = 0;
     tm.start();
     if (!fine_part) RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
-    RB_HIP(launch_look_list(part, ngroups, look_k, z.tk0, z.tk1, z.list, stream));
+    RB_HIP(launch_look_list(part, ngroups, look_k, z.list, stream));
     int64_t ex[kLookMax];
     int nd = 0;
     for (int d = 0; d < dmax; ++d) {
@@ -624,7 +621,10 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
         RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
         RB_HIP(hipStreamSynchronize(stream));
         st.sweeps++;
-        if (nd > 0) st.look_sweeps++;
+        if (nd > 0) {
+          st.look_sweeps++;
+          st.look_vectors += nd;
+        }
         ++m;
         fine_part = true;
         nspec = nd;

@@ -184,8 +184,7 @@ hipError_t launch_argmax_records(const ArgMax* partial, int64_t n, ArgMax* resul
 //     to c_out[v * M + j];
 //   launch_est_apply: acc_j += |c_j|^2 from stored coefficients (c == NULL:
 //     none) and the per-group partials of nrm - acc;
-//   launch_look_list: the best K of n partial records (K <= kLookListMax),
-//     through two scratch buffers of look_list_scratch(n, K) records;
+//   launch_look_list: the best K of n partial records (K <= kLookListMax);
 //   launch_rerank: for the K listed columns, c = e^H x_q and a = acc + |c|^2
 //     (acc_g[q] when first, else acc_l[slot]; a -> acc_l[slot]) and the argmax
 //     of nrm_q - a over listed columns neither masked nor in excl[0..nexcl);
@@ -198,9 +197,7 @@ hipError_t launch_sweep_look(const double2* S, int64_t N, int64_t M, int64_t ldS
                              ArgMax* partial, int64_t npartial_cap, hipStream_t s);
 hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask, const double2* c, int64_t M,
                             ArgMax* partial, int64_t npartial_cap, hipStream_t s);
-int64_t look_list_scratch(int64_t n, int K);
-hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* tmp0, ArgMax* tmp1, ArgMax* list,
-                            hipStream_t s);
+hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* list, hipStream_t s);
 int64_t rerank_partials(int K);
 hipError_t launch_rerank(const double2* X, int64_t N, int64_t ldX, const double2* e, const ArgMax* list, int K,
                          const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,

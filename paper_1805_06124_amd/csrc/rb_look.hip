@@ -151,57 +151,114 @@ __global__ __launch_bounds__(256) void k_est_apply(const double* __restrict__ nr
   }
 }
 
-// Bitonic sort of up to kTopN records per workgroup, best first (the vi
-// order: larger value, NaN above numbers, ties to the lower index, records
-// with index < 0 last); the first K go to out[blockIdx.x * K ...].
-constexpr int kTopN = 4096;
-constexpr int kTopThreads = 1024;
-__device__ __forceinline__ bool ranks_above(double av, int64_t ai, double bv, int64_t bi) {
-  if (ai < 0) return false;
-  if (bi < 0) return true;
-  const bool an = av != av, bn = bv != bv;
-  if (an != bn) return an;
-  if (!an && av != bv) return av > bv;
-  return ai < bi;
+// The candidate list: the best K of n partial records (index < 0: none),
+// best in the vi order (larger value, NaN above numbers, ties to the lower
+// index).  One workgroup selects by radix on an order-preserving 64-bit
+// key: eight rounds of 8-bit histograms find the K-th record's key; records
+// above it all enter the list, records equal to it fill the remaining places
+// in index order.  (Fewer rounds would not do: early in a run the best
+// thousands of estimates agree to 1e-4.)  Any list gives the same greedy;
+// only the number of correct predictions depends on it.
+constexpr int kSelThreads = 1024;
+constexpr int kSelRounds = 8;
+__device__ __forceinline__ uint64_t order_key(double v, int64_t i) {
+  if (i < 0) return 0;  // no record
+  if (v != v) return ~0ull;
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
 }
-__global__ __launch_bounds__(kTopThreads) void k_topk(const ArgMax* __restrict__ in, int64_t n, int K,
-                                                       ArgMax* __restrict__ out) {
-  __shared__ double sv[kTopN];
-  __shared__ int64_t si[kTopN];
-  const int64_t base = (int64_t)blockIdx.x * kTopN;
-  for (int t = threadIdx.x; t < kTopN; t += kTopThreads) {
-    const int64_t g = base + t;
-    if (g < n) {
-      sv[t] = in[g].v;
-      si[t] = in[g].i;
-    } else {
-      sv[t] = 0.0;
-      si[t] = -1;
+// exclusive prefix sum over the workgroup (thread order); *total = the sum
+__device__ __forceinline__ int block_exscan(int x, int* swave, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) swave[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < kSelThreads / 64; ++w) {
+      const int s = swave[w];
+      swave[w] = run;
+      run += s;
     }
+    swave[kSelThreads / 64] = run;
   }
   __syncthreads();
-  for (int size = 2; size <= kTopN; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < kTopN / 2; t += kTopThreads) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool best_first = (lo & size) == 0;
-        const bool swap = ranks_above(sv[hi], si[hi], sv[lo], si[lo]) == best_first;
-        if (swap) {
-          const double tv = sv[lo];
-          const int64_t ti = si[lo];
-          sv[lo] = sv[hi];
-          si[lo] = si[hi];
-          sv[hi] = tv;
-          si[hi] = ti;
-        }
+  const int r = swave[wave] + inc - x;
+  *total = swave[kSelThreads / 64];
+  __syncthreads();
+  return r;
+}
+__global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restrict__ in, int64_t n, int K,
+                                                            ArgMax* __restrict__ list) {
+  __shared__ unsigned hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int s_above, s_all;
+  __shared__ int swave[kSelThreads / 64 + 1];
+  // each thread owns one contiguous range of records (for the ordered fill)
+  const int64_t per = (n + kSelThreads - 1) / kSelThreads;
+  const int64_t t0 = (int64_t)threadIdx.x * per;
+  const int64_t t1 = t0 + per < n ? t0 + per : n;
+  uint64_t prefix = 0;
+  int shift = 64, above = 0, all = 0;
+  for (int r = 0; r < kSelRounds; ++r) {
+    shift -= 8;
+    for (int b = threadIdx.x; b < 256; b += kSelThreads) hist[b] = 0;
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+      const uint64_t key = order_key(in[t].v, in[t].i);
+      if (key == 0) continue;
+      if (r > 0 && (key >> (shift + 8)) != (prefix >> (shift + 8))) continue;
+      atomicAdd(&hist[(key >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int cum = above, b = 255;
+      for (; b >= 0; --b) {
+        if (cum + (int)hist[b] >= K) break;
+        cum += (int)hist[b];
       }
-      __syncthreads();
+      s_all = b < 0;
+      if (b >= 0) {
+        s_prefix = prefix | ((uint64_t)b << shift);
+        s_above = cum;
+      }
+    }
+    __syncthreads();
+    all = s_all;
+    if (all) break;
+    prefix = s_prefix;
+    above = s_above;
+  }
+  // the records of each class in this thread's range, then their places
+  int na = 0, nb = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint64_t key = order_key(in[t].v, in[t].i);
+    if (key == 0) continue;
+    if (all || (key >> shift) > (prefix >> shift)) ++na;
+    else if ((key >> shift) == (prefix >> shift)) ++nb;
+  }
+  int ta, tb;
+  int pa = block_exscan(na, swave, &ta);
+  int pb = ta + block_exscan(nb, swave, &tb);
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint64_t key = order_key(in[t].v, in[t].i);
+    if (key == 0) continue;
+    if (all || (key >> shift) > (prefix >> shift)) {
+      list[pa++] = in[t];
+    } else if ((key >> shift) == (prefix >> shift)) {
+      if (pb < K) list[pb] = in[t];
+      ++pb;
     }
   }
-  for (int r = threadIdx.x; r < K; r += kTopThreads) {
-    out[(int64_t)blockIdx.x * K + r].v = sv[r];
-    out[(int64_t)blockIdx.x * K + r].i = si[r];
+  const int filled = ta + tb < K ? ta + tb : K;
+  for (int r = filled + threadIdx.x; r < K; r += kSelThreads) {
+    list[r].v = 0.0;
+    list[r].i = -1;
   }
 }
 
@@ -294,29 +351,9 @@ hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask,
   return hipGetLastError();
 }
 
-int64_t look_list_scratch(int64_t n, int K) {
-  const int64_t first = (n + kTopN - 1) / kTopN * K;
-  return first > K ? first : K;
-}
-
-hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* tmp0, ArgMax* tmp1, ArgMax* list,
-                            hipStream_t s) {
-  if (K < 1 || K > kLookListMax) return hipErrorInvalidValue;
-  const ArgMax* src = partial;
-  ArgMax* bufs[2] = {tmp0, tmp1};
-  int which = 0;
-  // each level keeps the best K of every kTopN records (K <= kTopN / 2, so
-  // the count at least halves per level)
-  while (n > kTopN) {
-    const int64_t blocks = (n + kTopN - 1) / kTopN;
-    hipLaunchKernelGGL(k_topk, dim3((unsigned)blocks), dim3(kTopThreads), 0, s, src, n, K, bufs[which]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    src = bufs[which];
-    which ^= 1;
-    n = blocks * K;
-  }
-  hipLaunchKernelGGL(k_topk, dim3(1), dim3(kTopThreads), 0, s, src, n, K, list);
+hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* list, hipStream_t s) {
+  if (K < 1 || K > kLookListMax || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_look_list, dim3(1), dim3(kSelThreads), 0, s, partial, n, K, list);
   return hipGetLastError();
 }
 
