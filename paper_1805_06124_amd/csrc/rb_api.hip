@@ -158,6 +158,7 @@ struct ZScratch {
   // pivot lookahead: candidate list and its scratch, list-local sums, rerank partials
   ArgMax *list = nullptr, *rpart = nullptr, *lres = nullptr;
   double* acc_l = nullptr;
+  GsState* gst = nullptr;  // [0]: the step's own orthogonalisation, [1 + d]: prediction d
   // returns the bytes used (base == nullptr: sizing only); look_k = 0: no lookahead
   size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel, int look_k) {
     Carve c(base);
@@ -172,6 +173,7 @@ struct ZScratch {
     g = c.take<double2>(kcap > 0 ? kcap : 1);
     sq = c.take<double>(4);
     bad = c.take<int>(1);
+    gst = c.take<GsState>(kLookMax + 1);
     if (look_k > 0) {
       list = c.take<ArgMax>(look_k);
       acc_l = c.take<double>(look_k);
@@ -247,10 +249,12 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   }
   z.carve(ws, N, M, std::min(kmax, N), panel, z_look_k(o));
   HostWords hw;
-  if (hw.init(d_ws.p != nullptr, 96) != hipSuccess) return fail(RB_ENOMEM, "pinned host allocation failed");
+  if (hw.init(d_ws.p != nullptr, 96 + sizeof(GsState) * (kLookMax + 1)) != hipSuccess)
+    return fail(RB_ENOMEM, "pinned host allocation failed");
   ArgMax* h_res = hw.at<ArgMax>(0);     // 2 x 16 B
   double* h_sc = hw.at<double>(32);     // scalars
   int* h_bad = hw.at<int>(64);
+  GsState* h_gs = hw.at<GsState>(96);   // kLookMax + 1 records
 
   rb_stats st;
   std::memset(&st, 0, sizeof st);
@@ -436,89 +440,37 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
     return RB_OK;
   };
 
-  // Orthogonalisation of column Jc of X against E[:, 0..kk-1] into v
-  // (iterated classical Gram-Schmidt, Hoffmann's kappa criterion); the
-  // caller accepts it (launch_scale_into writes e = v / ||v||) or not.
-  struct Gs {
-    double r, s_norm;
-    int passes;
-    bool settled;  // the last pass met Hoffmann's criterion
-    const double* scale_src;
-  };
-  auto gs_run = [&](int64_t Jc, int64_t kk, Gs& g) -> int {
-    RB_HIP(hipMemcpyAsync(v, X + Jc * ldX, sizeof(double2) * N, hipMemcpyDeviceToDevice, stream));
-    // ||v|| before the first pass: the stored column (its norm differs from
-    // nrm[Jc] after a norms-only re-anchoring)
-    if (kk > 0) {
-      RB_HIP(launch_sqnorms_small(v, N, 1, N, sq + 1, stream));
-      RB_HIP(hipMemcpyAsync(&h_sc[0], sq + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
-    } else {
-      RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + Jc, sizeof(double), hipMemcpyDeviceToHost, stream));
-    }
-    RB_HIP(hipMemcpyAsync(&h_sc[1], nrm0 + Jc, sizeof(double), hipMemcpyDeviceToHost, stream));
-    RB_HIP(hipStreamSynchronize(stream));
-    double before = std::sqrt(h_sc[0]);
-    g.s_norm = std::sqrt(h_sc[1]);
-    double after = before;
-    g.scale_src = nrm + Jc;  // kk == 0: the exact column norm
-    g.passes = 0;
-    g.settled = true;
-    if (kk == 0) {
-      g.passes = 1;  // a pass against an empty basis changes nothing
-    } else {
-      g.settled = false;
-      while (g.passes < o.nu_max) {
-        RB_HIP(launch_gemv_ch(E, ldE, kk, v, N, 1, N, g_coef, stream));
-        RB_HIP(launch_gemv_n_sub(E, ldE, kk, g_coef, v, N, 1, N, stream));
-        RB_HIP(launch_sqnorms_small(v, N, 1, N, sq, stream));
-        RB_HIP(hipMemcpyAsync(&h_sc[2], sq, sizeof(double), hipMemcpyDeviceToHost, stream));
-        RB_HIP(hipStreamSynchronize(stream));
-        ++g.passes;
-        after = std::sqrt(h_sc[2]);
-        if (g.passes >= o.nu_min && after > before / o.kappa) {
-          g.settled = true;
-          break;
-        }
-        before = after;
-      }
-      g.scale_src = sq;
-    }
-    g.r = after;
+  // Orthogonalisation of the pivot (iterated classical Gram-Schmidt with
+  // Hoffmann's kappa criterion, Sec. 6.1.2) against E[:, 0..kk-1], kk >= 1,
+  // driven from the device (GsState): a step's own reads its outcome back
+  // once, a predicted one (rb_look.hip) not at all, and both run the same
+  // kernels.  jsrc (device) or jhost names the column; prev chains
+  // predictions; an accepted vector goes to E[:, kk].
+  auto gs_launch = [&](const ArgMax* jsrc, int64_t jhost, const GsState* prev, int64_t kk, GsState* gs) -> int {
+    RB_HIP(launch_gs_begin(X, ldX, N, jsrc, jhost, prev, nrm0, v, sq + 1, gs, stream));
+    for (int p = 0; p < o.nu_max; ++p)
+      RB_HIP(launch_gs_pass(E, ldE, kk, v, N, g_coef, sq, gs, o.nu_min, o.nu_max, o.kappa, stream));
+    RB_HIP(launch_gs_finish(gs, tol, sq, v, N, E + kk * ldE, stream));
     return RB_OK;
   };
-  auto gs_in_span = [&](const Gs& g) { return !(g.r > 64.0 * 0x1p-53 * g.s_norm); };
 
-  // Predict up to dmax next pivots before the sweep with E[:, k-1]: the
-  // best listed column after reranking with E[:, k-1] (then with each
-  // predicted vector in turn), orthogonalised into E[:, k + d] exactly as
-  // its own step would do it.  A prediction whose vector that step would
-  // not accept ends the chain (the step then reports it).
-  auto predict = [&](int dmax, int* nd_out) -> int {
-    *nd_out = 0;
+  // Predict the next dmax pivots before the sweep with E[:, k-1]: the best
+  // listed column after reranking with E[:, k-1] (then with each predicted
+  // vector in turn), orthogonalised into E[:, k + d] as its own step would
+  // do it; a prediction that step would not accept ends the chain.  No
+  // host round trip: the outcomes are read back with the sweep's argmax.
+  auto predict = [&](int dmax) -> int {
     tm.start();
     if (!fine_part) RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
     RB_HIP(launch_look_list(part, ngroups, look_k, z.list, stream));
-    int64_t ex[kLookMax];
-    int nd = 0;
     for (int d = 0; d < dmax; ++d) {
+      GsState* gd = z.gst + 1 + d;
       RB_HIP(launch_rerank(X, N, ldX, E + (k - 1 + d) * ldE, z.list, look_k, nrm, acc, z.acc_l, d == 0 ? 1 : 0,
-                           mask, ex, d, z.rpart, z.lres, stream));
-      RB_HIP(hipMemcpyAsync(h_res + 1, z.lres, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
-      RB_HIP(hipStreamSynchronize(stream));
-      const int64_t Jp = h_res[1].i;
-      if (Jp < 0 || std::isnan(h_res[1].v)) break;
-      Gs g;
-      int rc = gs_run(Jp, k + d, g);
+                           mask, z.gst + 1, d, z.rpart, z.lres, stream));
+      int rc = gs_launch(z.lres, -1, d > 0 ? gd - 1 : nullptr, k + d, gd);
       if (rc != RB_OK) return rc;
-      st.look_gs++;
-      if (!std::isfinite(g.r) || gs_in_span(g) || (!g.settled && g.r >= tol)) break;
-      RB_HIP(launch_scale_into(v, N, g.scale_src, E + (k + d) * ldE, stream));
-      spec[d] = Spec{Jp, g.r, g.passes};
-      ex[d] = Jp;
-      nd = d + 1;
     }
     lap(tm, &st.ms_look, nullptr);
-    *nd_out = nd;
     return RB_OK;
   };
 
@@ -563,67 +515,92 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
       nspec = spec_at = 0;
       // ---- 1. orthonormalise x_J (iterated Gram-Schmidt, kappa criterion) ----
       tm.start();
-      Gs g;
-      int rc = gs_run(J, k, g);
-      if (rc != RB_OK) return rc;
-      st.gs_passes += g.passes;
-      lap(tm, &st.ms_gs, slot(k, 0));
-      if (!std::isfinite(g.r)) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
-      if (gs_in_span(g)) {  // numerically in span(E)
-        status = RB_RANK;
-        break;
+      double r = 0.0;
+      int passes = 1;
+      if (k == 0) {
+        // against an empty basis: e = s_J / ||s_J|| with the exact norm
+        RB_HIP(hipMemcpyAsync(v, X + J * ldX, sizeof(double2) * N, hipMemcpyDeviceToDevice, stream));
+        RB_HIP(hipMemcpyAsync(&h_sc[0], nrm + J, sizeof(double), hipMemcpyDeviceToHost, stream));
+        RB_HIP(hipStreamSynchronize(stream));
+        r = std::sqrt(h_sc[0]);
+        if (!std::isfinite(r)) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
+        if (!(r > 0.0)) {
+          status = RB_RANK;
+          break;
+        }
+        RB_HIP(launch_scale_into(v, N, nrm + J, E, stream));
+      } else {
+        int rc = gs_launch(nullptr, J, nullptr, k, z.gst);
+        if (rc != RB_OK) return rc;
+        RB_HIP(hipMemcpyAsync(h_gs, z.gst, sizeof(GsState), hipMemcpyDeviceToHost, stream));
+        RB_HIP(hipStreamSynchronize(stream));
+        const GsState& g = *h_gs;
+        r = g.after;
+        passes = g.passes;
+        if (!g.finite) return fail_run(RB_ENONFINITE, "an orthogonalised pivot is not finite");
+        if (g.in_span) {  // numerically in span(E)
+          status = RB_RANK;
+          break;
+        }
+        if (!g.settled && r >= tol) {
+          char m2[160];
+          std::snprintf(m2, sizeof m2, "Gram-Schmidt of pivot %lld still shrank ||v|| by kappa after %d passes",
+                        (long long)J, passes);
+          return fail_run(RB_EBREAKDOWN, m2);
+        }
       }
-      if (!g.settled && g.r >= tol) {
-        char m2[160];
-        std::snprintf(m2, sizeof m2, "Gram-Schmidt of pivot %lld still shrank ||v|| by kappa after %d passes",
-                      (long long)J, g.passes);
-        return fail_run(RB_EBREAKDOWN, m2);
-      }
-      tm.start();
-      RB_HIP(launch_scale_into(v, N, g.scale_src, E + k * ldE, stream));
+      st.gs_passes += passes;
       RB_HIP(launch_fill(mask + J, (uint8_t)1, 1, stream));
       lap(tm, &st.ms_gs, slot(k, 0));
       piv[k] = J;
-      rho[k] = g.r;
-      if (nu) nu[k] = g.passes;
+      rho[k] = r;
+      if (nu) nu[k] = passes;
       ++k;
 
       // ---- 2. sweep with the new vector (panel row m) ----
       if (m == panel) {
-        rc = anchor(true, slot(k - 1, 2));
+        int rc = anchor(true, slot(k - 1, 2));
         if (rc != RB_OK) return rc;
         // the new vector has not been swept yet: the panel restarts at it
         a = k - 1;
       }
       if (fuse_next && m <= kFuseMaxM && norms_only_ok(est_prev)) {
-        rc = fused_sweep(slot(k - 1, 1), &est_max, &J);
+        int rc = fused_sweep(slot(k - 1, 1), &est_max, &J);
         if (rc != RB_OK) return rc;
       } else {
         // predicted vectors ride along in the same read of X, within the
-        // panel and the basis capacity
+        // panel and the basis capacity (one that was not accepted is read
+        // too and its coefficients are never used)
         const int64_t dmax = std::min<int64_t>(std::min<int64_t>(o.lookahead, panel - m - 1), kcap - k);
-        int nd = 0;
         if (dmax > 0) {
-          rc = predict((int)dmax, &nd);
-          if (rc != RB_OK) return rc;
+          int rc2 = predict((int)dmax);
+          if (rc2 != RB_OK) return rc2;
         }
         tm.start();
-        if (nd > 0)
-          RB_HIP(launch_sweep_look(X, N, M, ldX, E + (k - 1) * ldE, ldE, 1 + nd, nrm, acc, mask, cpan + m * M, part,
-                                   np, stream));
+        if (dmax > 0)
+          RB_HIP(launch_sweep_look(X, N, M, ldX, E + (k - 1) * ldE, ldE, 1 + (int)dmax, nrm, acc, mask,
+                                   cpan + m * M, part, np, stream));
         else
           RB_HIP(launch_sweep_z(X, N, M, ldX, E + (k - 1) * ldE, nrm, acc, mask, cpan + m * M, 1, part, np,
                                 nullptr, stream));
         const double ms_before = st.ms_sweep;
         lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
-        if (nd > 0) st.ms_look_sweep += st.ms_sweep - ms_before;
+        if (dmax > 0) st.ms_look_sweep += st.ms_sweep - ms_before;
         RB_HIP(launch_sweep_final(M, part, res, stream));
         RB_HIP(hipMemcpyAsync(h_res, res, sizeof(ArgMax), hipMemcpyDeviceToHost, stream));
+        if (dmax > 0)
+          RB_HIP(hipMemcpyAsync(h_gs + 1, z.gst + 1, sizeof(GsState) * dmax, hipMemcpyDeviceToHost, stream));
         RB_HIP(hipStreamSynchronize(stream));
         st.sweeps++;
-        if (nd > 0) {
+        int nd = 0;
+        if (dmax > 0) {
           st.look_sweeps++;
-          st.look_vectors += nd;
+          st.look_vectors += dmax;
+          for (int d = 0; d < (int)dmax; ++d) st.look_gs += h_gs[1 + d].live;
+          while (nd < (int)dmax && h_gs[1 + nd].accept) {
+            spec[nd] = Spec{h_gs[1 + nd].J, h_gs[1 + nd].after, h_gs[1 + nd].passes};
+            ++nd;
+          }
         }
         ++m;
         fine_part = true;

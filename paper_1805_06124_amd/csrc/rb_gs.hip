@@ -15,7 +15,9 @@ constexpr int kGsThreads = 256;
 // One workgroup per basis vector i: G[i + r*k] = e_i^H v_r for r < nv.
 __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restrict__ E, int64_t ldE, int64_t k,
                                                         const double2* __restrict__ V, int64_t ldV, int64_t nv,
-                                                        int64_t N, double2* __restrict__ G) {
+                                                        int64_t N, double2* __restrict__ G,
+                                                        const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = blockIdx.x;
   const double2* e = E + i * ldE;
   __shared__ double sre[kGsThreads / 64], sim[kGsThreads / 64];
@@ -104,16 +106,23 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
   }
 }
 
-// V[n + r*ldV] -= sum_i E[n + i*ldE] G[i + r*k]; one thread per row n,
-// one wave per workgroup (the grid spreads over more compute units), eight
-// basis vectors per thread in flight, added in the order of i.
-constexpr int kSubThreads = 64;
-__global__ __launch_bounds__(kSubThreads) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
-                                                            const double2* __restrict__ G, double2* __restrict__ V,
-                                                            int64_t ldV, int64_t nv, int64_t N) {
-  const int64_t n = (int64_t)blockIdx.x * kSubThreads + threadIdx.x;
-  if (n >= N) return;
-  constexpr int kMaxNv = 8;
+// V[n + r*ldV] -= sum_i E[n + i*ldE] G[i + r*k].  A workgroup owns 64 rows;
+// its kSubWaves waves split the basis vectors into contiguous ranges, each
+// lane sums its row over its range in the order of i (eight vectors in
+// flight), and the range sums are added in wave order through LDS.
+constexpr int kSubWaves = 4;
+constexpr int kMaxNv = 8;
+__global__ __launch_bounds__(kSubWaves * 64) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
+                                                               const double2* __restrict__ G, double2* __restrict__ V,
+                                                               int64_t ldV, int64_t nv, int64_t N,
+                                                               const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sre[kSubWaves][kMaxNv][64], sim[kSubWaves][kMaxNv][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t per = (k + kSubWaves - 1) / kSubWaves;
+  const int64_t i0 = wave * per;
+  const int64_t i1 = i0 + per < k ? i0 + per : k;
   double re[kMaxNv], im[kMaxNv];
 #pragma unroll
   for (int r = 0; r < kMaxNv; ++r) re[r] = im[r] = 0.0;
@@ -127,20 +136,36 @@ __global__ __launch_bounds__(kSubThreads) void k_gemv_n_sub(const double2* __res
       }
     }
   };
-  int64_t i = 0;
-  for (; i + 8 <= k; i += 8) {
-    double2 a[8];
+  if (n < N) {
+    int64_t i = i0;
+    for (; i + 8 <= i1; i += 8) {
+      double2 a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = E[n + (i + u) * ldE];
+      for (int u = 0; u < 8; ++u) a[u] = E[n + (i + u) * ldE];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) add(a[u], i + u);
+      for (int u = 0; u < 8; ++u) add(a[u], i + u);
+    }
+    for (; i < i1; ++i) add(E[n + i * ldE], i);
   }
-  for (; i < k; ++i) add(E[n + i * ldE], i);
 #pragma unroll
   for (int r = 0; r < kMaxNv; ++r) {
-    if (r < nv) {
-      double2 v = V[n + r * ldV];
-      V[n + r * ldV] = make_double2(v.x - re[r], v.y - im[r]);
+    sre[wave][r][lane] = re[r];
+    sim[wave][r][lane] = im[r];
+  }
+  __syncthreads();
+  if (wave == 0 && n < N) {
+#pragma unroll
+    for (int r = 0; r < kMaxNv; ++r) {
+      if (r < nv) {
+        double tr = sre[0][r][lane], ti = sim[0][r][lane];
+#pragma unroll
+        for (int w = 1; w < kSubWaves; ++w) {
+          tr += sre[w][r][lane];
+          ti += sim[w][r][lane];
+        }
+        const double2 v = V[n + r * ldV];
+        V[n + r * ldV] = make_double2(v.x - tr, v.y - ti);
+      }
     }
   }
 }
@@ -148,7 +173,8 @@ __global__ __launch_bounds__(kSubThreads) void k_gemv_n_sub(const double2* __res
 // out[r] = ||v_r||^2, accumulated exactly (double-double) and rounded once;
 // one workgroup per vector.
 __global__ __launch_bounds__(1024) void k_sqnorms_small(const double2* __restrict__ V, int64_t ldV, int64_t N,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const double2* v = V + (int64_t)blockIdx.x * ldV;
   dd s = {0.0, 0.0};
   for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
@@ -178,13 +204,126 @@ __global__ __launch_bounds__(kGsThreads) void k_scale_into(const double2* __rest
   out[n] = make_double2(a.x / r, a.y / r);
 }
 
+// ---- Gram-Schmidt driven from the device (GsState, see rb_internal.h) ----
+// Start: column J (from *jsrc, else jhost) of X into v, the state reset.
+// The orthogonalisation is live if J >= 0 and the previous one in a chain
+// (prev) was accepted.
+__global__ __launch_bounds__(kGsThreads) void k_gs_begin(const double2* __restrict__ X, int64_t ldX, int64_t N,
+                                                         const ArgMax* __restrict__ jsrc, int64_t jhost,
+                                                         const GsState* __restrict__ prev,
+                                                         const double* __restrict__ nrm0, double2* __restrict__ v,
+                                                         GsState* __restrict__ st) {
+  const int64_t J = jsrc ? jsrc->i : jhost;
+  const bool live = (prev ? prev->accept != 0 : true) && J >= 0;
+  const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+  if (live && n < N) v[n] = X[J * ldX + n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->J = J;
+    st->live = live;
+    st->done = !live;
+    st->passes = 0;
+    st->settled = 0;
+    st->accept = 0;
+    st->finite = 1;
+    st->in_span = 0;
+    st->s_norm2 = live ? nrm0[J] : 0.0;
+    st->before = st->after = 0.0;
+  }
+}
+// ||v|| before the first pass, from sq1 = ||v||^2
+__global__ void k_gs_setup(const double* __restrict__ sq1, GsState* __restrict__ st) {
+  if (!st->live) return;
+  st->before = st->after = sqrt(sq1[0]);
+}
+// After a pass (sq = ||v||^2): Hoffmann's criterion decides whether another
+// pass is due (Sec. 6.1.2), exactly as a host loop over the passes would.
+__global__ void k_gs_check(const double* __restrict__ sq, GsState* __restrict__ st, int nu_min, int nu_max,
+                           double kappa) {
+  if (st->done) return;
+  const double after = sqrt(sq[0]);
+  st->passes += 1;
+  st->after = after;
+  if (st->passes >= nu_min && after > st->before / kappa) {
+    st->settled = 1;
+    st->done = 1;
+  } else {
+    st->before = after;
+    if (st->passes >= nu_max) st->done = 1;
+  }
+}
+// The outcome: finite, numerically in span(E) (||v|| <= 64 u ||s_J||), and
+// accepted (live, finite, not in the span, settled unless ||v|| < tol);
+// an accepted vector is written as e = v / ||v|| into out.
+__global__ __launch_bounds__(kGsThreads) void k_gs_finish(GsState* __restrict__ st, double tol,
+                                                          const double* __restrict__ sq,
+                                                          const double2* __restrict__ v, int64_t N,
+                                                          double2* __restrict__ out) {
+  const double r = st->after;
+  const bool finite = __builtin_isfinite(r);
+  const bool in_span = !(r > 64.0 * 0x1p-53 * sqrt(st->s_norm2));
+  const bool ok = st->live && finite && !in_span && (st->settled || r < tol);
+  const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+  if (ok && n < N) {
+    const double rr = sqrt(sq[0]);
+    const double2 a = v[n];
+    out[n] = make_double2(a.x / rr, a.y / rr);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->finite = finite;
+    st->in_span = in_span;
+    st->accept = ok;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gs_begin(const double2* X, int64_t ldX, int64_t N, const ArgMax* jsrc, int64_t jhost,
+                           const GsState* prev, const double* nrm0, double2* v, double* sq1, GsState* st,
+                           hipStream_t s) {
+  const int64_t grid = (N + kGsThreads - 1) / kGsThreads;
+  hipLaunchKernelGGL(k_gs_begin, dim3((unsigned)grid), dim3(kGsThreads), 0, s, X, ldX, N, jsrc, jhost, prev, nrm0, v,
+                     st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sqnorms_small, dim3(1), dim3(1024), 0, s, v, N, N, sq1, &st->done);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gs_setup, dim3(1), dim3(1), 0, s, sq1, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_pass(const double2* E, int64_t ldE, int64_t kk, double2* v, int64_t N, double2* G, double* sq,
+                          GsState* st, int nu_min, int nu_max, double kappa, hipStream_t s) {
+  if (kk <= 0) return hipErrorInvalidValue;
+  const int32_t* skip = &st->done;
+  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)kk), dim3(kGsThreads), 0, s, E, ldE, kk, v, N, 1, N, G, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)((N + 63) / 64)), dim3(kSubWaves * 64), 0, s, E, ldE, kk, G, v, N,
+                     1, N, skip);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sqnorms_small, dim3(1), dim3(1024), 0, s, v, N, N, sq, skip);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(1), 0, s, sq, st, nu_min, nu_max, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_finish(GsState* st, double tol, const double* sq, const double2* v, int64_t N, double2* out,
+                            hipStream_t s) {
+  const int64_t grid = (N + kGsThreads - 1) / kGsThreads;
+  hipLaunchKernelGGL(k_gs_finish, dim3((unsigned)grid), dim3(kGsThreads), 0, s, st, tol, sq, v, N, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemv_ch(const double2* E, int64_t ldE, int64_t k, const double2* V, int64_t ldV, int64_t nv,
                           int64_t N, double2* G, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (nv > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kGsThreads), 0, s, E, ldE, k, V, ldV, nv, N, G);
+  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kGsThreads), 0, s, E, ldE, k, V, ldV, nv, N, G,
+                     static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
 
@@ -192,13 +331,15 @@ hipError_t launch_gemv_n_sub(const double2* E, int64_t ldE, int64_t k, const dou
                              int64_t nv, int64_t N, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (nv > 8) return hipErrorInvalidValue;
-  int64_t grid = (N + kSubThreads - 1) / kSubThreads;
-  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)grid), dim3(kSubThreads), 0, s, E, ldE, k, G, V, ldV, nv, N);
+  int64_t grid = (N + 63) / 64;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)grid), dim3(kSubWaves * 64), 0, s, E, ldE, k, G, V, ldV, nv, N,
+                     static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
 
 hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64_t N, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sqnorms_small, dim3((unsigned)nv), dim3(1024), 0, s, V, ldV, N, out);
+  hipLaunchKernelGGL(k_sqnorms_small, dim3((unsigned)nv), dim3(1024), 0, s, V, ldV, N, out,
+                     static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
 

@@ -187,7 +187,8 @@ hipError_t launch_argmax_records(const ArgMax* partial, int64_t n, ArgMax* resul
 //   launch_look_list: the best K of n partial records (K <= kLookListMax);
 //   launch_rerank: for the K listed columns, c = e^H x_q and a = acc + |c|^2
 //     (acc_g[q] when first, else acc_l[slot]; a -> acc_l[slot]) and the argmax
-//     of nrm_q - a over listed columns neither masked nor in excl[0..nexcl);
+//     of nrm_q - a over listed columns neither masked nor predicted before
+//     (chain[0..nprev).J; no candidate if chain[nprev-1] was not accepted);
 //     partial holds rerank_partials(K) records.
 constexpr int kPivotGroup = 16;
 constexpr int kLookMax = 4;
@@ -199,9 +200,10 @@ hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask,
                             ArgMax* partial, int64_t npartial_cap, hipStream_t s);
 hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* list, hipStream_t s);
 int64_t rerank_partials(int K);
+struct GsState;
 hipError_t launch_rerank(const double2* X, int64_t N, int64_t ldX, const double2* e, const ArgMax* list, int K,
                          const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
-                         const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* result, hipStream_t s);
+                         const GsState* chain, int nprev, ArgMax* partial, ArgMax* result, hipStream_t s);
 
 // mixed precision: complex64 sweep with FP32 basis copy -> kTop best
 // (est, index) in top[0..kTop) (descending, ties to the lower index)
@@ -231,6 +233,39 @@ hipError_t launch_gemv_n_sub(const double2* E, int64_t ldE, int64_t k, const dou
 hipError_t launch_sqnorms_small(const double2* V, int64_t ldV, int64_t nv, int64_t N, double* out,
                                 hipStream_t s);
 hipError_t launch_scale_into(const double2* v, int64_t N, const double* sq, double2* out, hipStream_t s);
+
+// The Gram-Schmidt of one pivot column driven from the device, so that a
+// chain of them (the pivot lookahead) runs without host round trips, and a
+// regular step reads its outcome back once.  launch_gs_begin copies column
+// J (*jsrc when jsrc != NULL, else jhost) of X into v and sets ||v|| before
+// the first pass (sq1 receives ||v||^2); prev (NULL: none) is the previous
+// link of a chain, whose rejection makes this one dead.  Each
+// launch_gs_pass is one classical pass against E[:, 0..kk-1], kk >= 1
+// (G: kk coefficients, sq: ||v||^2 after it), followed by Hoffmann's test;
+// passes after the test is met (or after nu_max) do nothing, so a caller
+// launches nu_max of them.  launch_gs_finish sets the outcome flags and
+// writes e = v / ||v|| into out when accepted.
+struct GsState {
+  double before;   // ||v|| before the pass under way
+  double after;    // ||v|| after the last pass: the residual rho of the pivot
+  double s_norm2;  // ||s_J||^2 of the original column (rank test)
+  int64_t J;       // the column (< 0: none)
+  int32_t passes;
+  int32_t done;     // no further pass runs
+  int32_t settled;  // the last pass met Hoffmann's criterion
+  int32_t live;     // this orthogonalisation runs at all
+  int32_t finite;   // ||v|| is finite
+  int32_t in_span;  // ||v|| <= 64 u ||s_J||: numerically in span(E)
+  int32_t accept;   // live, finite, not in the span, settled unless ||v|| < tol
+  int32_t pad;
+};
+hipError_t launch_gs_begin(const double2* X, int64_t ldX, int64_t N, const ArgMax* jsrc, int64_t jhost,
+                           const GsState* prev, const double* nrm0, double2* v, double* sq1, GsState* st,
+                           hipStream_t s);
+hipError_t launch_gs_pass(const double2* E, int64_t ldE, int64_t kk, double2* v, int64_t N, double2* G, double* sq,
+                          GsState* st, int nu_min, int nu_max, double kappa, hipStream_t s);
+hipError_t launch_gs_finish(GsState* st, double tol, const double* sq, const double2* v, int64_t N, double2* out,
+                            hipStream_t s);
 
 // Re-anchoring: W[:, j] = X[:, j] - sum_{i<m} E[:, i] C(i, j) with
 // C(i, j) = C[i*cI + j*cJ] (X may equal W; W == NULL: norms only),

@@ -298,22 +298,21 @@ __global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restr
 // One wave per listed column q: c = e^H x_q (the sweep's order), a = acc + |c|^2
 // (acc from acc_g[q] when first, else this column's slot of acc_l; a goes to
 // acc_l), and the workgroup's argmax of nrm_q - a over listed columns that are
-// neither masked nor among the nex excluded ones.
-struct Excl {
-  int64_t j[kLookMax];
-  int n;
-};
+// neither masked nor among the pivots predicted before (chain[0..nprev)).
+// If the last of those was not accepted the chain has ended: no candidate.
 constexpr int kRerankWaves = 4;
 constexpr int kRerankUnroll = 4;
 __global__ __launch_bounds__(kRerankWaves * 64) void k_rerank(
     const double2* __restrict__ X, int64_t N, int64_t ldX, const double2* __restrict__ e,
     const ArgMax* __restrict__ list, int K, const double* __restrict__ nrm, const double* __restrict__ acc_g,
-    double* __restrict__ acc_l, int first, const uint8_t* __restrict__ mask, Excl ex, ArgMax* __restrict__ partial) {
+    double* __restrict__ acc_l, int first, const uint8_t* __restrict__ mask, const GsState* __restrict__ chain,
+    int nprev, ArgMax* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int slot = blockIdx.x * kRerankWaves + wave;
+  const bool alive = nprev == 0 || chain[nprev - 1].accept != 0;
   vi best = {0.0, -1};
-  const int64_t q = slot < K ? list[slot].i : -1;
+  const int64_t q = (alive && slot < K) ? list[slot].i : -1;
   if (q >= 0) {
     const double2* x = X + q * ldX;
     double re = 0.0, im = 0.0;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(kRerankWaves * 64) void k_rerank(
     const double a = sweep_acc_add(first ? acc_g[q] : acc_l[slot], cr, ci);
     if (lane == 0) acc_l[slot] = a;
     bool skip = mask && mask[q];
-    for (int t = 0; t < ex.n; ++t) skip = skip || (ex.j[t] == q);
+    for (int t = 0; t < nprev; ++t) skip = skip || (chain[t].J == q);
     if (!skip) best = vi{nrm[q] - a, q};
   }
   // every lane of a wave holds the same record
@@ -394,14 +393,11 @@ int64_t rerank_partials(int K) { return (K + kRerankWaves - 1) / kRerankWaves; }
 
 hipError_t launch_rerank(const double2* X, int64_t N, int64_t ldX, const double2* e, const ArgMax* list, int K,
                          const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
-                         const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* result, hipStream_t s) {
-  if (K < 1 || nexcl < 0 || nexcl > kLookMax) return hipErrorInvalidValue;
-  Excl ex;
-  ex.n = nexcl;
-  for (int t = 0; t < kLookMax; ++t) ex.j[t] = t < nexcl ? excl[t] : -1;
+                         const GsState* chain, int nprev, ArgMax* partial, ArgMax* result, hipStream_t s) {
+  if (K < 1 || nprev < 0 || nprev > kLookMax || (nprev > 0 && !chain)) return hipErrorInvalidValue;
   const int64_t grid = rerank_partials(K);
   hipLaunchKernelGGL(k_rerank, dim3((unsigned)grid), dim3(kRerankWaves * 64), 0, s, X, N, ldX, e, list, K, nrm,
-                     acc_g, acc_l, first, mask, ex, partial);
+                     acc_g, acc_l, first, mask, chain, nprev, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   return launch_argmax_records(partial, grid, result, s);
