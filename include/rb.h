@@ -117,7 +117,7 @@ typedef struct rb_opts {
                          re-anchoring is accurate enough, fold it into the
                          next sweep (one read of the working matrix for
                          both); 0 = separate passes only.  Default 1. */
-  int32_t lookahead;  /* FP64 greedy: pivots predicted per sweep, 0..4.  Before
+  int32_t lookahead;  /* FP64 greedy: pivots predicted per sweep, 0..5.  Before
                          a sweep the next pivots are predicted from the
                          look_k columns with the best estimates: each listed
                          column's coefficient with the newest vector (and
@@ -131,7 +131,7 @@ typedef struct rb_opts {
                          sweep of its own.  Pivots, errors, residuals and
                          basis are bit-identical for every value; columns
                          of E past the returned k may hold predicted
-                         vectors.  0 = off.  Default 4. */
+                         vectors.  0 = off.  Default 5. */
   int32_t look_k;     /* length of the candidate list, 1..2048.  Default 2048. */
 } rb_opts;
 

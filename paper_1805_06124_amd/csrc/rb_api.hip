@@ -62,7 +62,7 @@ void rb_default_opts(rb_opts* o) {
   o->certify = 2;
   o->step_ms = nullptr;
   o->fuse = 1;
-  o->lookahead = 4;
+  o->lookahead = 5;
   o->look_k = 2048;
 }
 

@@ -120,7 +120,7 @@ struct Carve {
 // to pageable memory; no allocation).
 struct HostWords {
   HostBuf pinned;
-  alignas(64) unsigned char local[512];
+  alignas(64) unsigned char local[1024];
   unsigned char* p = local;
   // bytes <= sizeof local
   hipError_t init(bool may_alloc, size_t bytes) {

@@ -371,6 +371,7 @@ hipError_t launch_sweep_look(const double2* S, int64_t N, int64_t M, int64_t ldS
     case 3: return launch_sweep_look_t<3>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
     case 4: return launch_sweep_look_t<4>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
     case 5: return launch_sweep_look_t<5>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
+    case 6: return launch_sweep_look_t<6>(S, N, M, ldS, E, ldE, nrm, acc, mask, c_out, partial, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -35,7 +35,7 @@ def chirp_small():
     return w, _dev(oracle.chirp(w.params(), w.N, w.flo, w.fhi))
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 5])
 def test_lookahead_bit_identical(rb, chirp_small, depth):
     w, S = chirp_small
     g0 = rb.greedy(S, w.tol, w.kmax, lookahead=0)
@@ -53,7 +53,7 @@ def test_lookahead_bit_identical(rb, chirp_small, depth):
 def test_lookahead_list_lengths(rb, chirp_small, look_k):
     w, S = chirp_small
     g0 = rb.greedy(S, w.tol, w.kmax, lookahead=0)
-    g1 = rb.greedy(S, w.tol, w.kmax, lookahead=4, look_k=look_k)
+    g1 = rb.greedy(S, w.tol, w.kmax, lookahead=5, look_k=look_k)
     _same(g0, g1)
 
 
@@ -64,7 +64,7 @@ def test_lookahead_narrow_panel_and_theta(rb, chirp_small):
     w, S = chirp_small
     for kw in (dict(anchor_max=6), dict(theta=1e-3), dict(anchor_max=6, theta=1e-3, fuse=0)):
         g0 = rb.greedy(S, w.tol, w.kmax, W=torch.empty_like(S), lookahead=0, **kw)
-        g1 = rb.greedy(S, w.tol, w.kmax, W=torch.empty_like(S), lookahead=4, **kw)
+        g1 = rb.greedy(S, w.tol, w.kmax, W=torch.empty_like(S), lookahead=5, **kw)
         _same(g0, g1)
         assert g1["stats"]["anchors"] == g0["stats"]["anchors"]
 
@@ -85,7 +85,7 @@ def test_lookahead_gaussian_and_kmax(rb):
     S = _dev(ri.gaussian(3, 500, 700))
     for kmax in (37, 120):
         g0 = rb.greedy(S, 0.0, kmax, lookahead=0)
-        g1 = rb.greedy(S, 0.0, kmax, lookahead=4)
+        g1 = rb.greedy(S, 0.0, kmax, lookahead=5)
         _same(g0, g1)
         assert g1["k"] == kmax
 
@@ -94,6 +94,6 @@ def test_lookahead_breakdown(rb):
     theta, delta, n = 1.3, 1e-3, 80
     S = _dev(ri.kahan(n, theta, delta))
     g0 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=0)
-    g1 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=4)
+    g1 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=5)
     assert g1["status"] == "EBREAKDOWN"
     _same(g0, g1)
