@@ -132,7 +132,7 @@ typedef struct rb_opts {
                          basis are bit-identical for every value; columns
                          of E past the returned k may hold predicted
                          vectors.  0 = off.  Default 5. */
-  int32_t look_k;     /* length of the candidate list, 1..2048.  Default 2048. */
+  int32_t look_k;     /* length of the candidate list, 1..8192.  Default 4096. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */

@@ -63,7 +63,7 @@ void rb_default_opts(rb_opts* o) {
   o->step_ms = nullptr;
   o->fuse = 1;
   o->lookahead = 5;
-  o->look_k = 2048;
+  o->look_k = 4096;
 }
 
 const char* rb_strerror(int status) {

@@ -126,12 +126,12 @@ def test_workspace_sizes(L):
     assert L.rb_greedy_z_workspace(1000, 2000, -1, None) == 0
     o.anchor_max = 0
     assert L.rb_greedy_z_workspace(1000, 2000, 200, ctypes.byref(o)) == 0
-    # the pivot lookahead: depth 0..5, a list of 1..2048 columns (24 bytes
+    # the pivot lookahead: depth 0..5, a list of 1..8192 columns (24 bytes
     # each: the record and its running sum) only when the depth is nonzero
     L.rb_default_opts(ctypes.byref(o))
-    assert (o.lookahead, o.look_k) == (5, 2048)
-    for look, k_list, ok in ((0, 0, True), (5, 1, True), (5, 2048, True), (6, 2048, False), (-1, 2048, False),
-                             (3, 0, False), (3, 2049, False)):
+    assert (o.lookahead, o.look_k) == (5, 4096)
+    for look, k_list, ok in ((0, 0, True), (5, 1, True), (5, 8192, True), (6, 2048, False), (-1, 2048, False),
+                             (3, 0, False), (3, 8193, False)):
         o.lookahead, o.look_k = look, k_list
         assert (L.rb_greedy_z_workspace(1000, 2000, 200, ctypes.byref(o)) > 0) == ok, (look, k_list)
     o.lookahead, o.look_k = 0, 2048

@@ -49,7 +49,7 @@ def test_lookahead_bit_identical(rb, chirp_small, depth):
     assert st["look_steps"] <= depth * st["look_sweeps"]
 
 
-@pytest.mark.parametrize("look_k", [1, 3, 2048])
+@pytest.mark.parametrize("look_k", [1, 3, 8192])
 def test_lookahead_list_lengths(rb, chirp_small, look_k):
     w, S = chirp_small
     g0 = rb.greedy(S, w.tol, w.kmax, lookahead=0)
