@@ -156,7 +156,7 @@ struct ZScratch {
   double2 *cpan, *v, *g;
   int* bad;
   // pivot lookahead: candidate list and its scratch, list-local sums, rerank partials
-  ArgMax *list = nullptr, *rpart = nullptr, *lres = nullptr;
+  ArgMax *list = nullptr, *rpart = nullptr, *lres = nullptr, *coarse = nullptr;
   double* acc_l = nullptr;
   GsState* gst = nullptr;  // [0]: the step's own orthogonalisation, [1 + d]: prediction d
   // returns the bytes used (base == nullptr: sizing only); look_k = 0: no lookahead
@@ -176,6 +176,8 @@ struct ZScratch {
     gst = c.take<GsState>(kLookMax + 1);
     if (look_k > 0) {
       list = c.take<ArgMax>(look_k);
+      const int64_t nc = look_list_scratch((M + kPivotGroup - 1) / kPivotGroup);
+      if (nc > 0) coarse = c.take<ArgMax>(nc);
       acc_l = c.take<double>(look_k);
       rpart = c.take<ArgMax>(rerank_partials(look_k));
       lres = c.take<ArgMax>(1);
@@ -462,7 +464,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   auto predict = [&](int dmax) -> int {
     tm.start();
     if (!fine_part) RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
-    RB_HIP(launch_look_list(part, ngroups, look_k, z.list, stream));
+    RB_HIP(launch_look_list(part, ngroups, look_k, z.list, z.coarse, stream));
     for (int d = 0; d < dmax; ++d) {
       GsState* gd = z.gst + 1 + d;
       RB_HIP(launch_rerank(X, N, ldX, E + (k - 1 + d) * ldE, z.list, look_k, nrm, acc, z.acc_l, d == 0 ? 1 : 0,

@@ -190,10 +190,15 @@ __global__ __launch_bounds__(256) void k_est_apply(const double* __restrict__ nr
 // key: eight rounds of 8-bit histograms find the K-th record's key; records
 // above it all enter the list, records equal to it fill the remaining places
 // in index order.  (Fewer rounds would not do: early in a run the best
-// thousands of estimates agree to 1e-4.)  Any list gives the same greedy;
-// only the number of correct predictions depends on it.
+// thousands of estimates agree to 1e-4.)  The keys are read once, thread t
+// taking records t, t + 1024, ..., and kept in registers.  The list's order
+// is free (the reranking is order-independent), so records above the K-th
+// key take places from an LDS counter; only when the records equal to it
+// do not all fit are they placed in index order.  Any list gives the same
+// greedy; only the number of correct predictions depends on it.
 constexpr int kSelThreads = 1024;
 constexpr int kSelRounds = 8;
+constexpr int kSelPer = 32;  // records per thread kept in registers (n <= 32768)
 __device__ __forceinline__ uint64_t order_key(double v, int64_t i) {
   if (i < 0) return 0;  // no record
   if (v != v) return ~0ull;
@@ -230,23 +235,26 @@ __global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restr
                                                             ArgMax* __restrict__ list) {
   __shared__ unsigned hist[256];
   __shared__ uint64_t s_prefix;
-  __shared__ int s_above, s_all;
+  __shared__ int s_above, s_all, s_na, s_nb;
   __shared__ int swave[kSelThreads / 64 + 1];
-  // each thread owns one contiguous range of records (for the ordered fill)
-  const int64_t per = (n + kSelThreads - 1) / kSelThreads;
-  const int64_t t0 = (int64_t)threadIdx.x * per;
-  const int64_t t1 = t0 + per < n ? t0 + per : n;
+  uint64_t key[kSelPer];
+#pragma unroll
+  for (int q = 0; q < kSelPer; ++q) {
+    const int64_t t = threadIdx.x + (int64_t)kSelThreads * q;
+    key[q] = t < n ? order_key(in[t].v, in[t].i) : 0;
+  }
   uint64_t prefix = 0;
   int shift = 64, above = 0, all = 0;
   for (int r = 0; r < kSelRounds; ++r) {
     shift -= 8;
     for (int b = threadIdx.x; b < 256; b += kSelThreads) hist[b] = 0;
     __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) {
-      const uint64_t key = order_key(in[t].v, in[t].i);
-      if (key == 0) continue;
-      if (r > 0 && (key >> (shift + 8)) != (prefix >> (shift + 8))) continue;
-      atomicAdd(&hist[(key >> shift) & 255], 1u);
+#pragma unroll
+    for (int q = 0; q < kSelPer; ++q) {
+      const uint64_t k = key[q];
+      if (k == 0) continue;
+      if (r > 0 && (k >> (shift + 8)) != (prefix >> (shift + 8))) continue;
+      atomicAdd(&hist[(k >> shift) & 255], 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -267,32 +275,65 @@ __global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restr
     prefix = s_prefix;
     above = s_above;
   }
-  // the records of each class in this thread's range, then their places
-  int na = 0, nb = 0;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint64_t key = order_key(in[t].v, in[t].i);
-    if (key == 0) continue;
-    if (all || (key >> shift) > (prefix >> shift)) ++na;
-    else if ((key >> shift) == (prefix >> shift)) ++nb;
+  // records above the K-th key (or all, when fewer than K exist)
+  if (threadIdx.x == 0) {
+    s_na = 0;
+    s_nb = 0;
   }
-  int ta, tb;
-  int pa = block_exscan(na, swave, &ta);
-  int pb = ta + block_exscan(nb, swave, &tb);
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint64_t key = order_key(in[t].v, in[t].i);
-    if (key == 0) continue;
-    if (all || (key >> shift) > (prefix >> shift)) {
-      list[pa++] = in[t];
-    } else if ((key >> shift) == (prefix >> shift)) {
-      if (pb < K) list[pb] = in[t];
-      ++pb;
+  __syncthreads();
+  int nb_mine = 0;
+#pragma unroll
+  for (int q = 0; q < kSelPer; ++q) {
+    const uint64_t k = key[q];
+    if (k == 0) continue;
+    if (all || k > prefix) {
+      const int64_t t = threadIdx.x + (int64_t)kSelThreads * q;
+      list[atomicAdd(&s_na, 1)] = in[t];
+    } else if (k == prefix) {
+      ++nb_mine;
     }
   }
-  const int filled = ta + tb < K ? ta + tb : K;
+  int tb;
+  (void)block_exscan(nb_mine, swave, &tb);  // also orders the counter updates above
+  const int ta = all ? s_na : above;
+  if (!all && ta + tb <= K) {
+    // every record equal to the K-th key fits
+#pragma unroll
+    for (int q = 0; q < kSelPer; ++q) {
+      if (key[q] != 0 && key[q] == prefix) {
+        const int64_t t = threadIdx.x + (int64_t)kSelThreads * q;
+        list[ta + atomicAdd(&s_nb, 1)] = in[t];
+      }
+    }
+  } else if (!all) {
+    // ties at the K-th key: the lowest indices first, one block of records at a time
+    int placed = ta;
+#pragma unroll
+    for (int q = 0; q < kSelPer; ++q) {
+      const int mine = (key[q] != 0 && key[q] == prefix) ? 1 : 0;
+      int tot;
+      const int off = block_exscan(mine, swave, &tot);
+      if (mine && placed + off < K) list[placed + off] = in[threadIdx.x + (int64_t)kSelThreads * q];
+      placed += tot;
+    }
+  }
+  const int filled = all ? ta : (ta + tb < K ? ta + tb : K);
   for (int r = filled + threadIdx.x; r < K; r += kSelThreads) {
     list[r].v = 0.0;
     list[r].i = -1;
   }
+}
+
+// out[i] = the best of in[i f .. i f + f - 1] (vi order), i < nout
+__global__ __launch_bounds__(256) void k_coarsen(const ArgMax* __restrict__ in, int64_t n, int64_t f,
+                                                 ArgMax* __restrict__ out, int64_t nout) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nout) return;
+  vi best = {0.0, -1};
+  const int64_t j1 = (i + 1) * f < n ? (i + 1) * f : n;
+  for (int64_t j = i * f; j < j1; ++j) best = vi_max(best, vi{in[j].v, in[j].i});
+  out[i].v = best.v;
+  out[i].i = best.i;
 }
 
 // One wave per listed column q: c = e^H x_q (the sweep's order), a = acc + |c|^2
@@ -384,9 +425,24 @@ hipError_t launch_est_apply(const double* nrm, double* acc, const uint8_t* mask,
   return hipGetLastError();
 }
 
-hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* list, hipStream_t s) {
+int64_t look_list_scratch(int64_t n) { return n > (int64_t)kSelThreads * kSelPer ? (int64_t)kSelThreads * kSelPer : 0; }
+
+hipError_t launch_look_list(const ArgMax* partial, int64_t n, int K, ArgMax* list, ArgMax* scratch, hipStream_t s) {
+  constexpr int64_t kMaxRec = (int64_t)kSelThreads * kSelPer;
   if (K < 1 || K > kLookListMax || n < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_look_list, dim3(1), dim3(kSelThreads), 0, s, partial, n, K, list);
+  const ArgMax* src = partial;
+  if (n > kMaxRec) {
+    // more records than one selection holds: the maxima of f consecutive ones
+    if (!scratch) return hipErrorInvalidValue;
+    const int64_t f = (n + kMaxRec - 1) / kMaxRec;
+    const int64_t nout = (n + f - 1) / f;
+    hipLaunchKernelGGL(k_coarsen, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, partial, n, f, scratch, nout);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = scratch;
+    n = nout;
+  }
+  hipLaunchKernelGGL(k_look_list, dim3(1), dim3(kSelThreads), 0, s, src, n, K, list);
   return hipGetLastError();
 }
 

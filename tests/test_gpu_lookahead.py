@@ -97,3 +97,15 @@ def test_lookahead_breakdown(rb):
     g1 = rb.greedy(S, 0.0, n, nu_max=1, check=False, lookahead=5)
     assert g1["status"] == "EBREAKDOWN"
     _same(g0, g1)
+
+
+def test_lookahead_many_columns(rb):
+    """600,000 columns (37,500 groups of 16): the candidate list is selected
+    from the maxima of pairs of groups; still bit-identical."""
+    w = ri.WORKLOADS["chirp_10k_409600_c128"]
+    P = _dev(w.params(M=600_000))
+    S = rb.chirp_fill(P, 64, w.flo, w.fhi)
+    g0 = rb.greedy(S, 1e-9, 64, lookahead=0)
+    g1 = rb.greedy(S, 1e-9, 64)
+    _same(g0, g1)
+    assert g1["k"] > 20 and g1["stats"]["look_steps"] > 0
