@@ -81,6 +81,30 @@ def look_sweep_bytes(N, M, V):
     return 16 * N * M + 16 * N * V + (8 + 16 + 1 + 16 * V) * M
 
 
+def sweep_split(st, plain_bytes, look_bytes):
+    """The sweep kernels of a traced greedy run: the plain one and the one
+    carrying predicted vectors (rb_stats look_sweeps / ms_look_sweep); the
+    roofline is taken on the one with the larger share of the run."""
+    n_look = int(st["look_sweeps"])
+    n_plain = int(st["sweeps"]) - n_look
+    ms_look = st["ms_look_sweep"] / max(n_look, 1)
+    ms_plain = (st["ms_sweep"] - st["ms_look_sweep"]) / max(n_plain, 1)
+    v_mean = 1.0 + st["look_vectors"] / max(n_look, 1)
+    look_main = st["ms_look_sweep"] >= st["ms_sweep"] - st["ms_look_sweep"]
+    return {"look_main": look_main, "ms": ms_look if look_main else ms_plain,
+            "bytes": look_bytes(v_mean) if look_main else plain_bytes,
+            "sweeps": {"all": int(st["sweeps"]), "with_predictions": n_look, "plain": n_plain,
+                       "steps_from_predictions": int(st["look_steps"]),
+                       "predicted_orthogonalisations": int(st["look_gs"]),
+                       "vectors_per_predicting_sweep": v_mean,
+                       "ms_per_launch": {"look": ms_look if n_look else None, "plain": ms_plain if n_plain else None}}}
+
+
+def sweep32_look_bytes(N, M, V):
+    # as sweep32_bytes with V FP32 vectors read and V coefficient rows written
+    return 8 * N * M + 8 * N * V + (8 + 16 + 1 + 16 * V) * M
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -455,25 +479,29 @@ def cfg4_leg(rb, ri, args, log):
     g = runs[-1][1]
     gs = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=W32, ws=wsc, trace=True)
     st = gs["stats"]
-    ms = st["ms_sweep"] / max(st["sweeps"], 1)
-    by = sweep32_bytes(w.N, w.M)
+    sp = sweep_split(st, sweep32_bytes(w.N, w.M), lambda v: sweep32_look_bytes(w.N, w.M, v))
+    ms, by = sp["ms"], sp["bytes"]
+    kern32 = "k_sweep_c_look" if sp["look_main"] else "k_sweep_c"
     read = achievable_read(rb, S32)
     out = {"workload": w.name, "N": w.N, "M": w.M, "storage": "complex64", "tol": w.tol, "kmax": w.kmax,
            "value": sum(gg["k"] for _, gg in runs) / sum(dt for dt, _ in runs), "unit": "steps/s",
            "time_to_tol_s": t_run, "runs": run_spread(runs), "k": int(g["k"]), "status": g["status"],
            "err_final": float(g["err"][-1]), "anchors": int(g["stats"]["anchors"]),
            "exact_anchors": int(g["stats"]["regen_anchors"]), "misses": int(g["stats"]["misses"]),
-           "roofline": {"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+           "roofline": {"kernel": kern32, "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "ms_per_launch": ms, "bytes_per_launch": by, "achievable_read_GBs": read,
                         "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read},
            "breakdown_ms": {"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
+                            "lookahead_predict": st["ms_look"], "lookahead_apply": st["ms_apply"],
                             "total": st["ms_total"]},
+           "sweeps": sp["sweeps"],
            "per_step": step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "cfg4"),
            "workspace_bytes": int(wsc.numel())}
-    log("cfg4: k=%d, %.3f s per run = %.1f steps/s; sweep %.3f ms = %.1f GB/s; anchors %.1f ms (%d, exact %d)" % (
-        g["k"], t_run, out["value"], ms, out["roofline"]["achieved"], st["ms_anchor"], st["anchors"],
-        st["regen_anchors"]))
+    log("cfg4: k=%d, %.3f s per run = %.1f steps/s; %d sweeps (%d with predictions; %s %.3f ms = %.1f GB/s), "
+        "%d steps from predictions; anchors %.1f ms (%d, exact %d)" % (
+            g["k"], t_run, out["value"], st["sweeps"], st["look_sweeps"], kern32, ms, out["roofline"]["achieved"],
+            st["look_steps"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
     del S32, W32, wsc, runs, g, gs
     return out
 
@@ -639,8 +667,9 @@ def main():
         gs = rb.greedy_c(S32, tol, w.kmax, params, w.flo, w.fhi, W=W32, ws=wsc, trace=True)
         st = gs["stats"]
         mixed_steps = step_stats(gs["step_ms"], gs["k"], args.trace_jsonl, "mixed")
-        ms = st["ms_sweep"] / max(st["sweeps"], 1)
-        by = sweep32_bytes(w.N, w.M)
+        sp = sweep_split(st, sweep32_bytes(w.N, w.M), lambda v: sweep32_look_bytes(w.N, w.M, v))
+        ms, by = sp["ms"], sp["bytes"]
+        kern32 = "k_sweep_c_look" if sp["look_main"] else "k_sweep_c"
         read_after = achievable_read(rb, S32)
         log("plain streaming read of S32 after the greedy runs: %.1f GB/s" % read_after)
         read32 = max(read32, read_after)
@@ -650,18 +679,21 @@ def main():
                      anchors=int(g["stats"]["anchors"]), exact_anchors=int(g["stats"]["regen_anchors"]),
                      misses=int(g["stats"]["misses"]), orthogonality=orthogonality(g["E"]),
                      vs_fp64=None,
-                     roofline={"kernel": "k_sweep_c", "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
+                     roofline={"kernel": kern32, "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "traffic": measured_traffic("k_sweep_c", w.name.replace("c128", "c64")),
+                               "traffic": measured_traffic(kern32, w.name.replace("c128", "c64")),
                                "ms_per_launch": ms, "bytes_per_launch": by,
                                "achievable_read_GBs": read32,
                                "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read32},
                      breakdown_ms={"sweep": st["ms_sweep"], "confirm": st["ms_gs"], "anchor": st["ms_anchor"],
+                                   "lookahead_predict": st["ms_look"], "lookahead_apply": st["ms_apply"],
                                    "total": st["ms_total"]},
-                     per_step=mixed_steps, workspace_bytes=int(wsc.numel()))
-        log("mixed sweep: %.3f ms/launch, %.1f GB/s; confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (
-            ms, mixed["roofline"]["achieved"], st["ms_gs"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
+                     sweeps=sp["sweeps"], per_step=mixed_steps, workspace_bytes=int(wsc.numel()))
+        log("mixed sweeps: %d (%d with predictions, %.3f ms/launch for %s, %.1f GB/s); %d steps from predictions "
+            "(apply %.1f ms, predictions %.1f ms); confirm %.1f ms, anchors %.1f ms (%d, exact %d)" % (
+                st["sweeps"], st["look_sweeps"], ms, kern32, mixed["roofline"]["achieved"], st["look_steps"],
+                st["ms_apply"], st["ms_look"], st["ms_gs"], st["ms_anchor"], st["anchors"], st["regen_anchors"]))
         del W32, gs, runs, wsc
         torch.cuda.empty_cache()
         if fp64_trace is not None:

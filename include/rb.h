@@ -117,7 +117,7 @@ typedef struct rb_opts {
                          re-anchoring is accurate enough, fold it into the
                          next sweep (one read of the working matrix for
                          both); 0 = separate passes only.  Default 1. */
-  int32_t lookahead;  /* FP64 greedy: pivots predicted per sweep, 0..5.  Before
+  int32_t lookahead;  /* pivots predicted per sweep, 0..5.  Before
                          a sweep the next pivots are predicted from the
                          look_k columns with the best estimates: each listed
                          column's coefficient with the newest vector (and
@@ -128,10 +128,15 @@ typedef struct rb_opts {
                          matrix once for the newest and the predicted
                          vectors.  A step whose pivot was predicted then
                          takes that vector and its coefficients without a
-                         sweep of its own.  Pivots, errors, residuals and
-                         basis are bit-identical for every value; columns
-                         of E past the returned k may hold predicted
-                         vectors.  0 = off.  Default 5. */
+                         sweep of its own.  Mixed precision (rb_greedy_c):
+                         the prediction is the top-8 set of the complex64
+                         estimates and its FP64 confirmation; a step takes
+                         it when the set comes true (16-byte aligned
+                         complex64 columns with N even; otherwise no
+                         lookahead).  Pivots, errors, residuals and basis
+                         are bit-identical for every value; columns of E
+                         past the returned k may hold predicted vectors.
+                         0 = off.  Default 5. */
   int32_t look_k;     /* length of the candidate list, 1..8192.  Default 4096. */
 } rb_opts;
 

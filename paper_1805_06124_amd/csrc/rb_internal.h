@@ -78,6 +78,27 @@ hipError_t launch_sweep_c_final(int64_t M, ArgMax* partial, ArgMax* top, hipStre
 hipError_t launch_est_topk(const double* nrm, const double* acc, const uint8_t* mask, int64_t M, ArgMax* partial,
                            int64_t cap, ArgMax* top, hipStream_t s);
 int64_t sweep32_partials_needed(int64_t M);
+// Pivot lookahead of the mixed greedy (rb_sweep32.hip), the complex64 forms
+// of launch_sweep_look / launch_est_apply / launch_rerank: the same tile
+// arithmetic as launch_sweep_c on 16-byte aligned columns (even ldS) and
+// vectors (sweep_c_look_ok), top-8 candidates instead of one argmax.
+//   launch_sweep_c_look: V = 1 + d vectors e[v * ldv ..]; vector 0 advances
+//     acc and gives the top-8 (into top when != NULL), vector v's
+//     coefficients go to c_out[v * M + j];
+//   launch_est_apply32: acc += |c|^2 (c == NULL: none), top-8 into top;
+//   launch_rerank32: the listed columns' updated estimates (acc_l as in
+//     launch_rerank) and their top-8 into top, excluding masked columns and
+//     excl[0..nexcl); partial holds rerank32_partials(K) records.
+bool sweep_c_look_ok(const float2* S, int64_t ldS, const float2* e, int64_t ldv);
+hipError_t launch_sweep_c_look(const float2* S, int64_t N, int64_t M, int64_t ldS, const float2* e, int64_t ldv, int V,
+                               const double* nrm, double* acc, const uint8_t* mask, double2* c_out, ArgMax* partial,
+                               int64_t cap, ArgMax* top, hipStream_t s);
+hipError_t launch_est_apply32(const double* nrm, double* acc, const uint8_t* mask, const double2* c, int64_t M,
+                              ArgMax* partial, int64_t cap, ArgMax* top, hipStream_t s);
+int64_t rerank32_partials(int K);
+hipError_t launch_rerank32(const float2* X, int64_t N, int64_t ldX, const float2* e, const ArgMax* list, int K,
+                           const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
+                           const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* top, hipStream_t s);
 hipError_t launch_round32(const double2* x, int64_t N, float2* y, hipStream_t s);
 hipError_t launch_iota(int64_t* cols, int64_t start, int64_t n, hipStream_t s);
 // x[i] <- sqrt(x[i]), i < n

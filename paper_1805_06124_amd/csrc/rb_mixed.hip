@@ -98,9 +98,12 @@ struct CScratch {
   ArgMax *part, *top;
   double2 *cpan, *V, *G;
   int64_t* cols;
-  float2* e32;
+  float2* e32;  // the sweep's FP32 vector, then (lookahead) the predicted ones, N apart
   int* bad;
-  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel) {
+  // pivot lookahead: candidate list, list-local sums, rerank partials, predicted top-8
+  ArgMax *list = nullptr, *rpart = nullptr, *ptop = nullptr, *coarse = nullptr;
+  double* acc_l = nullptr;
+  size_t carve(void* base, int64_t N, int64_t M, int64_t kcap, int64_t panel, int look_k) {
     Carve c(base);
     nrm = c.take<double>(M);
     acc = c.take<double>(M);
@@ -112,8 +115,16 @@ struct CScratch {
     G = c.take<double2>((size_t)(kcap > 0 ? kcap : 1) * kTop);
     sq = c.take<double>(2 * kTop);
     cols = c.take<int64_t>(kTop);
-    e32 = c.take<float2>(N);
+    e32 = c.take<float2>((size_t)N * (look_k > 0 ? 1 + kLookMax : 1));
     bad = c.take<int>(1);
+    if (look_k > 0) {
+      list = c.take<ArgMax>(look_k);
+      acc_l = c.take<double>(look_k);
+      rpart = c.take<ArgMax>(rerank32_partials(look_k));
+      ptop = c.take<ArgMax>(kTop);
+      const int64_t nc = look_list_scratch((M + 15) / 16);
+      if (nc > 0) coarse = c.take<ArgMax>(nc);
+    }
     return c.used;
   }
 };
@@ -131,15 +142,17 @@ struct CRegen {
 
 bool c_opts_ok(const rb_opts& o) {
   return o.kappa > 1.0 && o.nu_max >= 1 && o.nu_min >= 1 && o.nu_min <= o.nu_max && o.theta32 > 0.0 &&
-         o.theta32 < 1.0 && o.anchor_max >= 1 && o.regen_chunk >= 1;
+         o.theta32 < 1.0 && o.anchor_max >= 1 && o.regen_chunk >= 1 && o.lookahead >= 0 &&
+         o.lookahead <= kLookMax && (o.lookahead == 0 || (o.look_k >= 1 && o.look_k <= kLookListMax));
 }
+int c_look_k(const rb_opts& o) { return o.lookahead > 0 ? o.look_k : 0; }
 
 // both parts, 256-byte aligned one after the other
 size_t c_ws_bytes(int64_t N, int64_t M, int64_t kcap, const rb_opts& o, size_t* base_bytes) {
   CScratch c;
   CRegen r;
   const int64_t chunk = o.regen_chunk < M ? o.regen_chunk : M;
-  const size_t b = (c.carve(nullptr, N, M, kcap, o.anchor_max) + 255) & ~static_cast<size_t>(255);
+  const size_t b = (c.carve(nullptr, N, M, kcap, o.anchor_max, c_look_k(o)) + 255) & ~static_cast<size_t>(255);
   if (base_bytes) *base_bytes = b;
   return b + r.carve(nullptr, N, kcap, chunk);
 }
@@ -198,11 +211,11 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       std::snprintf(m, sizeof m, "workspace of %zu bytes, %zu needed", ws_bytes, need);
       return fail(RB_ENOMEM, m);
     }
-    z.carve(ws, N, M, kcap, panel);
+    z.carve(ws, N, M, kcap, panel, c_look_k(o));
     rg.carve(static_cast<char*>(ws) + base_bytes, N, kcap, chunk);
   } else {
     RB_ALLOC(d_ws, base_bytes);
-    z.carve(d_ws.p, N, M, kcap, panel);
+    z.carve(d_ws.p, N, M, kcap, panel, c_look_k(o));
   }
   HostWords hw;
   const size_t h_bytes = sizeof(ArgMax) * kTop + sizeof(double) * 2 * kTop + sizeof(int64_t) * kTop + 64;
@@ -269,7 +282,10 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
   bool rank_flag = false, settled_b = true;
   const double* sq_final = sq;
   // slot_ms: where the confirmation's time goes (the vector it chooses)
-  auto confirm = [&](int64_t kcur, double* slot_ms) -> int {
+  // spec: a predicted set (rb_look.hip's lookahead): a non-finite candidate
+  // ends the prediction instead of the run, and the time and passes count
+  // as prediction
+  auto confirm = [&](int64_t kcur, double* slot_ms, bool spec = false) -> int {
     tm.start();
     int nv = 0;
     for (int r = 0; r < kTop; ++r)
@@ -279,7 +295,7 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     rank_flag = false;
     settled_b = true;
     if (nv == 0) {
-      lap(tm, &st.ms_gs, slot_ms);
+      lap(tm, spec ? &st.ms_look : &st.ms_gs, slot_ms);
       return RB_OK;
     }
     RB_HIP(hipMemcpyAsync(cols, h_cols, sizeof(int64_t) * nv, hipMemcpyHostToDevice, stream));
@@ -292,7 +308,13 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     for (int r = 0; r < nv; ++r) {
       orig[r] = before[r] = after[r] = std::sqrt(h_sq[r]);
       settled[r] = true;
-      if (!std::isfinite(orig[r])) return fail_run(RB_ENONFINITE, "a regenerated candidate is not finite");
+      if (!std::isfinite(orig[r])) {
+        if (spec) {
+          lap(tm, &st.ms_look, nullptr);
+          return RB_OK;  // Jbest < 0: no prediction
+        }
+        return fail_run(RB_ENONFINITE, "a regenerated candidate is not finite");
+      }
     }
     sq_final = sq;
     passes = 1;
@@ -316,9 +338,19 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       }
       sq_final = sq + kTop;
     }
-    st.gs_passes += passes;
+    if (spec) {
+      st.look_gs++;
+    } else {
+      st.gs_passes += passes;
+    }
     for (int r = 0; r < nv; ++r)
-      if (!std::isfinite(after[r])) return fail_run(RB_ENONFINITE, "an orthogonalised candidate is not finite");
+      if (!std::isfinite(after[r])) {
+        if (spec) {
+          lap(tm, &st.ms_look, nullptr);
+          return RB_OK;
+        }
+        return fail_run(RB_ENONFINITE, "an orthogonalised candidate is not finite");
+      }
     int b = 0;
     for (int r = 1; r < nv; ++r)
       if (after[r] > after[b] || (after[r] == after[b] && h_cols[r] < h_cols[b])) b = r;
@@ -327,9 +359,28 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     rbest = after[b];
     settled_b = settled[b];
     rank_flag = !(rbest > 64.0 * 0x1p-53 * orig[b]);
-    lap(tm, &st.ms_gs, slot_ms);
+    lap(tm, spec ? &st.ms_look : &st.ms_gs, slot_ms);
     return RB_OK;
   };
+
+  // ---- pivot lookahead (rb_look.hip): predictions spec[spec_at .. nspec)
+  // made at the last sweep, each with its predicted top-8 set, the outcome
+  // of confirming that set, its vector in E[:, k + d] and its coefficients
+  // in panel row m + d.  A step takes a prediction when the top-8 set of
+  // the estimates equals the predicted one: its confirmation, which
+  // depends on nothing else, then gives the same pivot and vector. ----
+  struct Spec32 {
+    int64_t top[kTop];
+    int64_t J;
+    double r;
+    int passes;
+    bool settled, rank;
+  };
+  Spec32 spec[kLookMax];
+  int nspec = 0, spec_at = 0;
+  bool taken = false;  // the step about to start was predicted
+  const int look_k = c_look_k(o);
+  const int64_t ngroups = (M + 15) / 16;
 
   // ---- re-anchoring ----
   auto ensure_w = [&]() -> int {
@@ -341,6 +392,8 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     return RB_OK;
   };
   auto anchor = [&](bool exact, double* slot_ms) -> int {
+    nspec = spec_at = 0;
+    taken = false;
     tm.start();
     int rc = ensure_w();
     if (rc != RB_OK) return rc;
@@ -398,6 +451,54 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     return RB_OK;
   };
 
+  // Predict the next dmax steps before the sweep with e32 (E[:, k-1]): the
+  // top-8 of the listed columns after reranking with the newest FP32 vector
+  // (then with each predicted one), confirmed in FP64 against E[:, 0..k+d-1]
+  // exactly as its step would confirm it; the chosen vector goes to
+  // E[:, k + d] and its FP32 copy to e32 + (d + 1) N.  A prediction its step
+  // would not accept ends the chain.  Returns the number made.
+  auto predict = [&](int dmax, int* nd_out) -> int {
+    *nd_out = 0;
+    tm.start();
+    RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
+    RB_HIP(launch_look_list(part, ngroups, look_k, z.list, z.coarse, stream));
+    lap(tm, &st.ms_look, nullptr);
+    int64_t ex[kLookMax];
+    int nd = 0;
+    for (int d = 0; d < dmax; ++d) {
+      tm.start();
+      RB_HIP(launch_rerank32(X32, N, ldX, e32 + d * N, z.list, look_k, nrm, acc, z.acc_l, d == 0 ? 1 : 0, mask, ex, d,
+                             z.rpart, z.ptop, stream));
+      RB_HIP(hipMemcpyAsync(h_top, z.ptop, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
+      RB_HIP(hipStreamSynchronize(stream));
+      lap(tm, &st.ms_look, nullptr);
+      if (h_top[0].i < 0 || std::isnan(h_top[0].v)) break;
+      int rc2 = confirm(k + d, nullptr, true);
+      if (rc2 != RB_OK) return rc2;
+      if (Jbest < 0 || rank_flag || (!settled_b && rbest >= tol)) break;
+      tm.start();
+      RB_HIP(launch_scale_into(V + slot_b * N, N, sq_final + slot_b, E + (k + d) * ldE, stream));
+      RB_HIP(launch_round32(E + (k + d) * ldE, N, e32 + (d + 1) * N, stream));
+      lap(tm, &st.ms_look, nullptr);
+      Spec32& sp = spec[d];
+      for (int r = 0; r < kTop; ++r) sp.top[r] = h_top[r].i;
+      sp.J = Jbest;
+      sp.r = rbest;
+      sp.passes = passes;
+      sp.settled = settled_b;
+      sp.rank = rank_flag;
+      ex[d] = Jbest;
+      nd = d + 1;
+    }
+    *nd_out = nd;
+    return RB_OK;
+  };
+  auto same_top = [&](const Spec32& sp) -> bool {
+    for (int r = 0; r < kTop; ++r)
+      if (h_top[r].i != sp.top[r]) return false;
+    return true;
+  };
+
   int rc = confirm(0, slot(0, 0));
   if (rc != RB_OK) return rc;
   err[0] = (Jbest >= 0) ? rbest : 0.0;
@@ -445,10 +546,14 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     }
     rc = check_breakdown();
     if (rc != RB_OK) return rc;
-    // ---- 1. the confirmed candidate becomes e_k ----
+    // ---- 1. the confirmed candidate becomes e_k (a predicted one is there already) ----
     tm.start();
-    RB_HIP(launch_scale_into(V + slot_b * N, N, sq_final + slot_b, E + k * ldE, stream));
-    RB_HIP(launch_round32(E + k * ldE, N, e32, stream));
+    bool step_taken = taken;
+    taken = false;
+    if (!step_taken) {
+      RB_HIP(launch_scale_into(V + slot_b * N, N, sq_final + slot_b, E + k * ldE, stream));
+      RB_HIP(launch_round32(E + k * ldE, N, e32, stream));
+    }
     RB_HIP(launch_fill(mask + Jbest, (uint8_t)1, 1, stream));
     lap(tm, &st.ms_gs, slot(k, 0));
     piv[k] = Jbest;
@@ -458,28 +563,77 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
     certified = false;
 
     // ---- 2. complex64 sweep with the FP32 copy (panel row m) ----
+    bool apply_taken = step_taken;
     if (m == panel) {
       rc = anchor(choose_exact(rbest), slot(k - 1, 2));
       if (rc != RB_OK) return rc;
       a = k - 1;  // the new vector has not been swept yet
+      apply_taken = false;
     }
-    tm.start();
-    RB_HIP(launch_sweep_c(X32, N, M, ldX, e32, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr, stream));
-    lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
-    RB_HIP(launch_sweep_c_final(M, part, top, stream));
-    RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
-    RB_HIP(hipStreamSynchronize(stream));
-    st.sweeps++;
-    ++m;
+    if (apply_taken) {
+      // its coefficients are panel row m already
+      tm.start();
+      RB_HIP(launch_est_apply32(nrm, acc, mask, cpan + m * M, M, part, np, top, stream));
+      RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
+      RB_HIP(hipStreamSynchronize(stream));
+      lap(tm, &st.ms_apply, slot(k - 1, 1));
+      st.look_steps++;
+      ++m;
+    } else {
+      if (step_taken) {  // a re-anchoring came in between: sweep with its FP32 copy
+        RB_HIP(launch_round32(E + (k - 1) * ldE, N, e32, stream));
+      }
+      nspec = spec_at = 0;
+      int64_t dmax = 0;
+      if (look_k > 0 && sweep_c_look_ok(X32, ldX, e32, N))
+        dmax = std::min<int64_t>(std::min<int64_t>(o.lookahead, panel - m - 1), kcap - k);
+      int nd = 0;
+      if (dmax > 0) {
+        rc = predict((int)dmax, &nd);
+        if (rc != RB_OK) return rc;
+      }
+      tm.start();
+      if (nd > 0)
+        RB_HIP(launch_sweep_c_look(X32, N, M, ldX, e32, N, 1 + nd, nrm, acc, mask, cpan + m * M, part, np, nullptr,
+                                   stream));
+      else
+        RB_HIP(launch_sweep_c(X32, N, M, ldX, e32, nrm, acc, mask, cpan + m * M, 1, part, np, nullptr, stream));
+      const double ms_before = st.ms_sweep;
+      lap(tm, &st.ms_sweep, slot(k - 1, 1));  // the sweep kernel alone
+      if (nd > 0) {
+        st.ms_look_sweep += st.ms_sweep - ms_before;
+        st.look_sweeps++;
+        st.look_vectors += nd;
+      }
+      RB_HIP(launch_sweep_c_final(M, part, top, stream));
+      RB_HIP(hipMemcpyAsync(h_top, top, sizeof(ArgMax) * kTop, hipMemcpyDeviceToHost, stream));
+      RB_HIP(hipStreamSynchronize(stream));
+      st.sweeps++;
+      ++m;
+      nspec = nd;
+      spec_at = 0;
+    }
     if (h_top[0].i >= 0 && std::isnan(h_top[0].v)) return fail_run(RB_ENONFINITE, "a swept estimate is not finite");
     if (h_top[0].i >= 0 && h_top[0].v < o.theta32 * A_w) {
       rc = anchor(choose_exact(std::sqrt(h_top[0].v > 0.0 ? h_top[0].v : 0.0)), slot(k - 1, 2));
       if (rc != RB_OK) return rc;
     }
-    // ---- 3. FP64 confirmation of the candidates ----
+    // ---- 3. FP64 confirmation of the candidates (or the predicted one's) ----
     const int64_t top1 = h_top[0].i;
-    rc = confirm(k, slot(k, 0));
-    if (rc != RB_OK) return rc;
+    if (spec_at < nspec && same_top(spec[spec_at])) {
+      const Spec32& sp = spec[spec_at++];
+      Jbest = sp.J;
+      rbest = sp.r;
+      passes = sp.passes;
+      settled_b = sp.settled;
+      rank_flag = sp.rank;
+      st.gs_passes += passes;
+      taken = true;
+    } else {
+      nspec = spec_at = 0;
+      rc = confirm(k, slot(k, 0));
+      if (rc != RB_OK) return rc;
+    }
     if (Jbest >= 0 && Jbest != top1) st.misses++;
     err[k] = (Jbest >= 0) ? rbest : 0.0;
   }

@@ -95,9 +95,13 @@ __device__ void block_top_merge(TopList& L, ArgMax* __restrict__ out) {
   }
 }
 
+// conj(e) s added to an FP32 row-tile sum with explicit fused multiply-adds:
+// every kernel that forms a complex64 sweep coefficient (the sweep, the
+// sweep with predicted vectors, the reranking of a candidate list) rounds
+// it the same way, rows in the same order per lane.
 __device__ __forceinline__ void cmac_conj32(const float2 e, const float2 s, float& re, float& im) {
-  re += e.x * s.x + e.y * s.y;
-  im += e.x * s.y - e.y * s.x;
+  re = __builtin_fmaf(e.y, s.y, __builtin_fmaf(e.x, s.x, re));
+  im = __builtin_fmaf(-e.y, s.x, __builtin_fmaf(e.x, s.y, im));
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c(
     if (lane == c) {
       vi cand = {0.0, -1};
       if (j < M) {
-        const double a = acc[j] + (cr * cr + ci * ci);
+        const double a = sweep_acc_add(acc[j], cr, ci);
         acc[j] = a;
         if (kStoreC) c_out[j * ldc] = make_double2(cr, ci);
         if (!(mask && mask[j])) cand = {nrm[j] - a, j};
@@ -211,6 +215,234 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c(
       partial[blockIdx.x * kTop + r].i = L.i[r];
     }
   }
+}
+
+// ---- pivot lookahead for the mixed greedy (see rb_look.hip for the FP64
+// form).  All three kernels follow k_sweep_c<true, true>'s arithmetic for a
+// column: per lane, FP32 sums over each 512-row tile (rows base + 2 (64 u +
+// lane) + {0, 1}, u = 0..3, in that order) added to FP64 totals, the rows past
+// the last full tile (n = nfull + lane + 64 t) summed in FP32 and added once,
+// then wave_sum and sweep_acc_add.  So a coefficient, an estimate and the
+// top-8 set come out the same whichever of them forms it. ----
+
+// c_v(j) = e_v^H x_j for the V complex64 vectors e[v * ldv ..], every column j
+// (16-byte aligned columns and vectors, even ldS); vector 0 advances acc and
+// gives the per-workgroup top-8 (the partial layout of k_sweep_c), vector v
+// its coefficients c_out[v * M + j].
+template <int V>
+__global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
+    const float2* __restrict__ S, int64_t N, int64_t M, int64_t ldS, const float2* __restrict__ e, int64_t ldv,
+    const double* __restrict__ nrm, double* __restrict__ acc, const uint8_t* __restrict__ mask,
+    double2* __restrict__ c_out, ArgMax* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t col0 = (int64_t)blockIdx.x * kS32ColsPerBlock + (int64_t)wave * kS32Cols;
+  const float2* cp[kS32Cols];
+#pragma unroll
+  for (int c = 0; c < kS32Cols; ++c) {
+    int64_t j = col0 + c;
+    if (j > M - 1) j = M - 1;
+    cp[c] = S + j * ldS;
+  }
+  double re[V][kS32Cols], im[V][kS32Cols];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int c = 0; c < kS32Cols; ++c) re[v][c] = im[v][c] = 0.0;
+  constexpr int kU = kS32Unroll / 2;
+  constexpr int kStep = 64 * kS32Unroll;
+  const int64_t nfull = (N / kStep) * kStep;
+  for (int64_t base = 0; base < nfull; base += kStep) {
+    f4v sv[kS32Cols][kU];
+#pragma unroll
+    for (int c = 0; c < kS32Cols; ++c)
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        sv[c][u] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(cp[c] + base + 2 * (64 * u + lane)));
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      f4v ev[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) ev[u] = *reinterpret_cast<const f4v*>(e + v * ldv + base + 2 * (64 * u + lane));
+#pragma unroll
+      for (int c = 0; c < kS32Cols; ++c) {
+        float r32 = 0.f, i32 = 0.f;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          cmac_conj32(make_float2(ev[u].x, ev[u].y), make_float2(sv[c][u].x, sv[c][u].y), r32, i32);
+          cmac_conj32(make_float2(ev[u].z, ev[u].w), make_float2(sv[c][u].z, sv[c][u].w), r32, i32);
+        }
+        re[v][c] += (double)r32;
+        im[v][c] += (double)i32;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    float r32[kS32Cols], i32[kS32Cols];
+#pragma unroll
+    for (int c = 0; c < kS32Cols; ++c) r32[c] = i32[c] = 0.f;
+    for (int64_t n = nfull + lane; n < N; n += 64) {
+      const float2 ev = e[v * ldv + n];
+#pragma unroll
+      for (int c = 0; c < kS32Cols; ++c) cmac_conj32(ev, ld_stream(cp[c] + n), r32[c], i32[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kS32Cols; ++c) {
+      re[v][c] += (double)r32[c];
+      im[v][c] += (double)i32[c];
+    }
+  }
+  __shared__ vi scand[kS32ColsPerBlock];
+#pragma unroll
+  for (int c = 0; c < kS32Cols; ++c) {
+    const int64_t j = col0 + c;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double cr = wave_sum(re[v][c]);
+      const double ci = wave_sum(im[v][c]);
+      if (v == 0) {
+        if (lane == c) {
+          vi cand = {0.0, -1};
+          if (j < M) {
+            const double a = sweep_acc_add(acc[j], cr, ci);
+            acc[j] = a;
+            c_out[j] = make_double2(cr, ci);
+            if (!(mask && mask[j])) cand = {nrm[j] - a, j};
+          }
+          scand[wave * kS32Cols + c] = cand;
+        }
+      } else if (j < M && lane == c + kS32Cols * v) {
+        c_out[v * M + j] = make_double2(cr, ci);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TopList L;
+    L.clear();
+    for (int t = 0; t < kS32ColsPerBlock; ++t) L.insert(scand[t].v, scand[t].i);
+#pragma unroll
+    for (int r = 0; r < kTop; ++r) {
+      partial[blockIdx.x * kTop + r].v = L.v[r];
+      partial[blockIdx.x * kTop + r].i = L.i[r];
+    }
+  }
+}
+
+// A step taken from a prediction: acc_j += |c_j|^2 (c == NULL: none) and the
+// top-8 of nrm_j - acc_j per group of kS32ColsPerBlock columns (the partial
+// layout of k_sweep_c).
+__global__ __launch_bounds__(256) void k_est_apply32(const double* __restrict__ nrm, double* __restrict__ acc,
+                                                     const uint8_t* __restrict__ mask, const double2* __restrict__ c,
+                                                     int64_t M, ArgMax* __restrict__ partial) {
+  __shared__ vi sc[256];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  vi cand = {0.0, -1};
+  if (j < M) {
+    double a = acc[j];
+    if (c) {
+      const double2 cj = c[j];
+      a = sweep_acc_add(a, cj.x, cj.y);
+      acc[j] = a;
+    }
+    if (!(mask && mask[j])) cand = {nrm[j] - a, j};
+  }
+  sc[threadIdx.x] = cand;
+  __syncthreads();
+  constexpr int kGroups = 256 / kS32ColsPerBlock;
+  if (threadIdx.x < kGroups) {
+    const int64_t g = (int64_t)blockIdx.x * kGroups + threadIdx.x;
+    if (g * kS32ColsPerBlock < M) {
+      TopList L;
+      L.clear();
+      for (int t = 0; t < kS32ColsPerBlock; ++t) L.insert(sc[threadIdx.x * kS32ColsPerBlock + t].v,
+                                                          sc[threadIdx.x * kS32ColsPerBlock + t].i);
+#pragma unroll
+      for (int r = 0; r < kTop; ++r) {
+        partial[g * kTop + r].v = L.v[r];
+        partial[g * kTop + r].i = L.i[r];
+      }
+    }
+  }
+}
+
+// One wave per listed column q of the complex64 matrix: its coefficient with
+// e and a = acc + |c|^2 (acc_g[q] when first, else the column's slot of
+// acc_l; a -> acc_l), and the top-8 of nrm_q - a per workgroup over listed
+// columns neither masked nor among the ex.n pivots predicted before.
+struct Excl32 {
+  int64_t j[kLookMax];
+  int n;
+};
+constexpr int kRerank32Waves = 4;
+__global__ __launch_bounds__(kRerank32Waves * 64) void k_rerank32(
+    const float2* __restrict__ X, int64_t N, int64_t ldX, const float2* __restrict__ e,
+    const ArgMax* __restrict__ list, int K, const double* __restrict__ nrm, const double* __restrict__ acc_g,
+    double* __restrict__ acc_l, int first, const uint8_t* __restrict__ mask, Excl32 ex,
+    ArgMax* __restrict__ partial) {
+  __shared__ vi scand[kRerank32Waves];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * kRerank32Waves + wave;
+  const int64_t q = slot < K ? list[slot].i : -1;
+  vi cand = {0.0, -1};
+  if (q >= 0) {
+    const float2* x = X + q * ldX;
+    constexpr int kU = kS32Unroll / 2;
+    constexpr int kStep = 64 * kS32Unroll;
+    const int64_t nfull = (N / kStep) * kStep;
+    double re = 0.0, im = 0.0;
+    for (int64_t base = 0; base < nfull; base += kStep) {
+      f4v ev[kU], sv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        ev[u] = *reinterpret_cast<const f4v*>(e + base + 2 * (64 * u + lane));
+        sv[u] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(x + base + 2 * (64 * u + lane)));
+      }
+      float r32 = 0.f, i32 = 0.f;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        cmac_conj32(make_float2(ev[u].x, ev[u].y), make_float2(sv[u].x, sv[u].y), r32, i32);
+        cmac_conj32(make_float2(ev[u].z, ev[u].w), make_float2(sv[u].z, sv[u].w), r32, i32);
+      }
+      re += (double)r32;
+      im += (double)i32;
+    }
+    float r32 = 0.f, i32 = 0.f;
+    for (int64_t n = nfull + lane; n < N; n += 64) cmac_conj32(e[n], ld_stream(x + n), r32, i32);
+    re += (double)r32;
+    im += (double)i32;
+    const double cr = wave_sum(re);
+    const double ci = wave_sum(im);
+    const double a = sweep_acc_add(first ? acc_g[q] : acc_l[slot], cr, ci);
+    if (lane == 0) acc_l[slot] = a;
+    bool skip = mask && mask[q];
+    for (int t = 0; t < ex.n; ++t) skip = skip || (ex.j[t] == q);
+    if (!skip) cand = vi{nrm[q] - a, q};
+  }
+  if (lane == 0) scand[wave] = cand;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TopList L;
+    L.clear();
+    for (int t = 0; t < kRerank32Waves; ++t) L.insert(scand[t].v, scand[t].i);
+#pragma unroll
+    for (int r = 0; r < kTop; ++r) {
+      partial[blockIdx.x * kTop + r].v = L.v[r];
+      partial[blockIdx.x * kTop + r].i = L.i[r];
+    }
+  }
+}
+
+template <int V>
+hipError_t launch_sweep_c_look_t(const float2* S, int64_t N, int64_t M, int64_t ldS, const float2* e, int64_t ldv,
+                                 const double* nrm, double* acc, const uint8_t* mask, double2* c_out,
+                                 ArgMax* partial, hipStream_t s) {
+  const int64_t grid = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
+  hipLaunchKernelGGL(k_sweep_c_look<V>, dim3((unsigned)grid), dim3(kS32Waves * 64), 0, s, S, N, M, ldS, e, ldv, nrm,
+                     acc, mask, c_out, partial);
+  return hipGetLastError();
 }
 
 // kTop best of in[0..n) per workgroup chunk -> out[blockIdx.x * kTop ..]
@@ -321,6 +553,56 @@ hipError_t launch_iota(int64_t* cols, int64_t start, int64_t n, hipStream_t s) {
 hipError_t launch_round32(const double2* x, int64_t N, float2* y, hipStream_t s) {
   hipLaunchKernelGGL(k_round32, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, x, N, y);
   return hipGetLastError();
+}
+
+bool sweep_c_look_ok(const float2* S, int64_t ldS, const float2* e, int64_t ldv) {
+  return (ldS % 2 == 0) && (reinterpret_cast<uintptr_t>(S) % 16 == 0) && (reinterpret_cast<uintptr_t>(e) % 16 == 0) &&
+         (ldv % 2 == 0);
+}
+
+hipError_t launch_sweep_c_look(const float2* S, int64_t N, int64_t M, int64_t ldS, const float2* e, int64_t ldv, int V,
+                               const double* nrm, double* acc, const uint8_t* mask, double2* c_out, ArgMax* partial,
+                               int64_t cap, ArgMax* top, hipStream_t s) {
+  const int64_t grid = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
+  if (grid * kTop + kTop * 256 > cap || !sweep_c_look_ok(S, ldS, e, ldv)) return hipErrorInvalidValue;
+  hipError_t err;
+  switch (V) {
+    case 2: err = launch_sweep_c_look_t<2>(S, N, M, ldS, e, ldv, nrm, acc, mask, c_out, partial, s); break;
+    case 3: err = launch_sweep_c_look_t<3>(S, N, M, ldS, e, ldv, nrm, acc, mask, c_out, partial, s); break;
+    case 4: err = launch_sweep_c_look_t<4>(S, N, M, ldS, e, ldv, nrm, acc, mask, c_out, partial, s); break;
+    case 5: err = launch_sweep_c_look_t<5>(S, N, M, ldS, e, ldv, nrm, acc, mask, c_out, partial, s); break;
+    case 6: err = launch_sweep_c_look_t<6>(S, N, M, ldS, e, ldv, nrm, acc, mask, c_out, partial, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess || !top) return err;
+  return topk_final(partial, grid * kTop, partial + grid * kTop, top, s);
+}
+
+hipError_t launch_est_apply32(const double* nrm, double* acc, const uint8_t* mask, const double2* c, int64_t M,
+                              ArgMax* partial, int64_t cap, ArgMax* top, hipStream_t s) {
+  const int64_t groups = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
+  if (groups * kTop + kTop * 256 > cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_est_apply32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, nrm, acc, mask, c, M, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return topk_final(partial, groups * kTop, partial + groups * kTop, top, s);
+}
+
+int64_t rerank32_partials(int K) { return kTop * ((K + kRerank32Waves - 1) / kRerank32Waves) + kTop * 256; }
+
+hipError_t launch_rerank32(const float2* X, int64_t N, int64_t ldX, const float2* e, const ArgMax* list, int K,
+                           const double* nrm, const double* acc_g, double* acc_l, int first, const uint8_t* mask,
+                           const int64_t* excl, int nexcl, ArgMax* partial, ArgMax* top, hipStream_t s) {
+  if (K < 1 || nexcl < 0 || nexcl > kLookMax || !sweep_c_look_ok(X, ldX, e, 2)) return hipErrorInvalidValue;
+  Excl32 ex;
+  ex.n = nexcl;
+  for (int t = 0; t < kLookMax; ++t) ex.j[t] = t < nexcl ? excl[t] : -1;
+  const int64_t grid = (K + kRerank32Waves - 1) / kRerank32Waves;
+  hipLaunchKernelGGL(k_rerank32, dim3((unsigned)grid), dim3(kRerank32Waves * 64), 0, s, X, N, ldX, e, list, K, nrm,
+                     acc_g, acc_l, first, mask, ex, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return topk_final(partial, grid * kTop, partial + grid * kTop, top, s);
 }
 
 }  // namespace rb
