@@ -225,15 +225,24 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c(
 // then wave_sum and sweep_acc_add.  So a coefficient, an estimate and the
 // top-8 set come out the same whichever of them forms it. ----
 
+typedef __attribute__((address_space(3))) void lds_void32_t;
+typedef __attribute__((address_space(1))) const void global_void32_t;
+
 // c_v(j) = e_v^H x_j for the V complex64 vectors e[v * ldv ..], every column j
 // (16-byte aligned columns and vectors, even ldS); vector 0 advances acc and
 // gives the per-workgroup top-8 (the partial layout of k_sweep_c), vector v
-// its coefficients c_out[v * M + j].
+// its coefficients c_out[v * M + j].  The vectors' rows of each 512-row tile
+// are shared by the workgroup's waves through LDS, copied by direct
+// global-to-LDS loads one tile ahead into one of two buffers, as in the FP64
+// k_sweep_look.
 template <int V>
 __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
     const float2* __restrict__ S, int64_t N, int64_t M, int64_t ldS, const float2* __restrict__ e, int64_t ldv,
     const double* __restrict__ nrm, double* __restrict__ acc, const uint8_t* __restrict__ mask,
     double2* __restrict__ c_out, ArgMax* __restrict__ partial) {
+  constexpr int kU = kS32Unroll / 2;
+  constexpr int kRows = 64 * kS32Unroll;
+  __shared__ __align__(16) float2 sbuf[2][V][kRows];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t col0 = (int64_t)blockIdx.x * kS32ColsPerBlock + (int64_t)wave * kS32Cols;
@@ -249,10 +258,17 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
   for (int v = 0; v < V; ++v)
 #pragma unroll
     for (int c = 0; c < kS32Cols; ++c) re[v][c] = im[v][c] = 0.0;
-  constexpr int kU = kS32Unroll / 2;
-  constexpr int kStep = 64 * kS32Unroll;
-  const int64_t nfull = (N / kStep) * kStep;
-  for (int64_t base = 0; base < nfull; base += kStep) {
+  const int64_t nch = N / kRows;
+  // rows [ch kRows, (ch + 1) kRows) of every vector: 64 lanes x 16 B per load
+  auto fill = [&](int64_t ch, float2 (*dst)[kRows]) {
+    for (int p = wave; p < V * kU; p += kS32Waves) {
+      const int v = p / kU, u = p % kU;
+      const float2* src = e + v * ldv + ch * kRows + 2 * (64 * u + lane);
+      __builtin_amdgcn_global_load_lds((global_void32_t*)src, (lds_void32_t*)&dst[v][2 * 64 * u], 16, 0, 0);
+    }
+  };
+  auto tile = [&](int64_t ch, float2 (*cur)[kRows]) {
+    const int64_t base = ch * kRows;
     f4v sv[kS32Cols][kU];
 #pragma unroll
     for (int c = 0; c < kS32Cols; ++c)
@@ -263,7 +279,7 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
     for (int v = 0; v < V; ++v) {
       f4v ev[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) ev[u] = *reinterpret_cast<const f4v*>(e + v * ldv + base + 2 * (64 * u + lane));
+      for (int u = 0; u < kU; ++u) ev[u] = *reinterpret_cast<const f4v*>(&cur[v][2 * (64 * u + lane)]);
 #pragma unroll
       for (int c = 0; c < kS32Cols; ++c) {
         float r32 = 0.f, i32 = 0.f;
@@ -275,8 +291,18 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
         re[v][c] += (double)r32;
         im[v][c] += (double)i32;
       }
+      // one vector's rows in registers at a time
+      __builtin_amdgcn_sched_barrier(0);
     }
+  };
+  if (nch > 0) fill(0, sbuf[0]);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) fill(ch + 1, sbuf[(ch + 1) & 1]);
+    tile(ch, sbuf[ch & 1]);
+    __syncthreads();
   }
+  const int64_t nfull = nch * kRows;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     float r32[kS32Cols], i32[kS32Cols];
