@@ -46,12 +46,16 @@ FP64_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each
 # scaled by the same counter's reading for a plain 4 GiB device copy (see
-# profiles/k_sweep_z_chirp_10k_409600_c128_hbm_counters.md), keyed by a hash
-# of the kernel's source file and the device header it inlines: reported
-# only while those sources are unchanged.
+# profiles/k_sweep_look_chirp_10k_409600_c128_hbm_counters.md and
+# profiles/k_sweep_c_look_chirp_10k_409600_c64_hbm_counters.md), keyed by a
+# hash of the kernel's source file and the device header it inlines:
+# reported only while those sources are unchanged.  The lookahead sweeps'
+# figures are for six vectors.
 MEASURED_TRAFFIC = {
-    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_internal.h"), "9dc42129b4fb7b99", 65554852960),
-    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_internal.h"), "e2a92cdfe45d490d", 32789033483),
+    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_device.h"), "d1a4878fc3822bbc", 65553550569),
+    ("k_sweep_look", "chirp_10k_409600_c128"): (("rb_look.hip", "rb_device.h"), "95969117f1d393ba", 65597510056),
+    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 32788490950),
+    ("k_sweep_c_look", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 36644102230),
 }
 
 
@@ -206,8 +210,8 @@ def pmc_probe(rb, w, params, log):
     """Kernels for the HBM byte counters: one plain device-to-device copy of
     4 GiB (known traffic: 4 GiB read, 4 GiB written) to calibrate the
     counters, then three fused sweeps of the workload in complex128, the
-    first 12 greedy steps (sweeps with predicted vectors), and three sweeps
-    in complex64."""
+    first 12 greedy steps (sweeps with predicted vectors), three sweeps in
+    complex64 and the first 12 steps of the mixed greedy."""
     import torch
     n = (4 << 30) // 16
     src = torch.ones(n, dtype=torch.complex128, device=params.device)
@@ -236,6 +240,12 @@ def pmc_probe(rb, w, params, log):
     for i in range(3):
         est, J = rb.sweep_c(S32, e32, nrm, acc, None, c)
         log("complex64 sweep %d: J=%d bytes=%d" % (i, J[0], sweep32_bytes(w.N, w.M)))
+    # the first 12 steps of the mixed greedy: complex64 sweeps that carry
+    # predicted vectors
+    gc = rb.greedy_c(S32, 0.0, 12, params, w.flo, w.fhi, collect_stats=1)
+    st = gc["stats"]
+    log("mixed greedy, 12 steps: %d sweeps with predictions carrying %d vectors, %d plain" % (
+        st["look_sweeps"], st["look_vectors"], st["sweeps"] - st["look_sweeps"]))
 
 
 def timed_runs(fn, steps, warmup, log, tag):
