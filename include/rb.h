@@ -128,8 +128,9 @@ typedef struct rb_opts {
                          matrix once for the newest and the predicted
                          vectors.  A step whose pivot was predicted then
                          takes that vector and its coefficients without a
-                         sweep of its own.  Mixed precision (rb_greedy_c):
-                         the prediction is the top-8 set of the complex64
+                         sweep of its own.  Mixed precision (rb_greedy_c,
+                         depth lookahead32): the prediction is the top-8
+                         set of the complex64
                          estimates and its FP64 confirmation; a step takes
                          it when the set comes true (16-byte aligned
                          complex64 columns with N even; otherwise no
@@ -138,6 +139,16 @@ typedef struct rb_opts {
                          past the returned k may hold predicted vectors.
                          0 = off.  Default 5. */
   int32_t look_k;     /* length of the candidate list, 1..8192.  Default 4096. */
+  int32_t lookahead32; /* mixed greedy (rb_greedy_c): its own depth, 0..5,
+                          or -1 = 2 below 1,000,000 columns and 5 from
+                          there (lookahead applies to the FP64 greedy).
+                          The complex64 sweep is bound by FP32
+                          multiply-adds, so each predicted vector costs
+                          more there, and each prediction is an FP64
+                          confirmation of eight regenerated columns, a
+                          fixed cost that longer reads amortise (measured
+                          on 10,000 rows: depth 2 best at 409,600 columns,
+                          5 at 1,638,400).  Default -1. */
 } rb_opts;
 
 /* Per-call statistics (host struct, optional). */

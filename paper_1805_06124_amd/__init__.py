@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("theta", ctypes.c_double), ("anchor_max", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("theta32", ctypes.c_double), ("regen_chunk", ctypes.c_int32), ("certify", ctypes.c_int32),
                 ("step_ms", ctypes.c_void_p), ("fuse", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("look_k", ctypes.c_int32)]
+                ("look_k", ctypes.c_int32), ("lookahead32", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -64,6 +64,7 @@ void rb_default_opts(rb_opts* o) {
   o->fuse = 1;
   o->lookahead = 5;
   o->look_k = 4096;
+  o->lookahead32 = -1;
 }
 
 const char* rb_strerror(int status) {

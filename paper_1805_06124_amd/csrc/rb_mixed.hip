@@ -142,10 +142,12 @@ struct CRegen {
 
 bool c_opts_ok(const rb_opts& o) {
   return o.kappa > 1.0 && o.nu_max >= 1 && o.nu_min >= 1 && o.nu_min <= o.nu_max && o.theta32 > 0.0 &&
-         o.theta32 < 1.0 && o.anchor_max >= 1 && o.regen_chunk >= 1 && o.lookahead >= 0 &&
-         o.lookahead <= kLookMax && (o.lookahead == 0 || (o.look_k >= 1 && o.look_k <= kLookListMax));
+         o.theta32 < 1.0 && o.anchor_max >= 1 && o.regen_chunk >= 1 && o.lookahead32 >= -1 &&
+         o.lookahead32 <= kLookMax && (o.lookahead32 == 0 || (o.look_k >= 1 && o.look_k <= kLookListMax));
 }
-int c_look_k(const rb_opts& o) { return o.lookahead > 0 ? o.look_k : 0; }
+// the mixed greedy's prediction depth (lookahead32 = -1: by the column count)
+int c_depth(const rb_opts& o, int64_t M) { return o.lookahead32 >= 0 ? o.lookahead32 : (M < 1000000 ? 2 : 5); }
+int c_look_k(const rb_opts& o) { return o.lookahead32 != 0 ? o.look_k : 0; }
 
 // both parts, 256-byte aligned one after the other
 size_t c_ws_bytes(int64_t N, int64_t M, int64_t kcap, const rb_opts& o, size_t* base_bytes) {
@@ -586,7 +588,7 @@ int rb_greedy_c(const void* S32_, int64_t N, int64_t M, int64_t ldS, double tol,
       nspec = spec_at = 0;
       int64_t dmax = 0;
       if (look_k > 0 && sweep_c_look_ok(X32, ldX, e32, N))
-        dmax = std::min<int64_t>(std::min<int64_t>(o.lookahead, panel - m - 1), kcap - k);
+        dmax = std::min<int64_t>(std::min<int64_t>(c_depth(o, M), panel - m - 1), kcap - k);
       int nd = 0;
       if (dmax > 0) {
         rc = predict((int)dmax, &nd);

@@ -129,7 +129,7 @@ def test_workspace_sizes(L):
     # the pivot lookahead: depth 0..5, a list of 1..8192 columns (24 bytes
     # each: the record and its running sum) only when the depth is nonzero
     L.rb_default_opts(ctypes.byref(o))
-    assert (o.lookahead, o.look_k) == (5, 4096)
+    assert (o.lookahead, o.look_k, o.lookahead32) == (5, 4096, -1)
     for look, k_list, ok in ((0, 0, True), (5, 1, True), (5, 8192, True), (6, 2048, False), (-1, 2048, False),
                              (3, 0, False), (3, 8193, False)):
         o.lookahead, o.look_k = look, k_list

@@ -111,7 +111,8 @@ def test_lookahead_many_columns(rb):
     assert g1["k"] > 20 and g1["stats"]["look_steps"] > 0
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(anchor_max=6), dict(lookahead=2, look_k=3)])
+@pytest.mark.parametrize("kw", [dict(), dict(lookahead32=1), dict(lookahead32=5), dict(anchor_max=6, lookahead32=4),
+                                dict(lookahead32=2, look_k=3)])
 def test_mixed_lookahead_bit_identical(rb, kw):
     """The mixed greedy: a step is taken from a prediction when the top-8
     set of the complex64 estimates equals the predicted one; pivots, errors,
@@ -120,8 +121,8 @@ def test_mixed_lookahead_bit_identical(rb, kw):
     w = ri.WORKLOADS["chirp_small_c128"]
     P = _dev(w.params())
     S32 = rb.chirp_fill(P, w.N, w.flo, w.fhi, dtype=torch.complex64)
-    g0 = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=torch.empty_like(S32), lookahead=0,
-                     **{a: b for a, b in kw.items() if a not in ("lookahead", "look_k")})
+    g0 = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=torch.empty_like(S32), lookahead32=0,
+                     **{a: b for a, b in kw.items() if a not in ("lookahead32", "look_k")})
     g1 = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=torch.empty_like(S32), **kw)
     _same(g0, g1)
     for key in ("anchors", "regen_anchors", "misses"):
