@@ -49,20 +49,20 @@ FP64_PEAK_TFLOPS = 78.6
 # profiles/k_sweep_look_chirp_10k_409600_c128_hbm_counters.md and
 # profiles/k_sweep_c_look_chirp_10k_409600_c64_hbm_counters.md), keyed by a
 # hash of the kernel's source file and the device header it inlines:
-# reported only while those sources are unchanged.  The lookahead sweeps'
-# figures are for six vectors.
+# reported only while those sources are unchanged and for launches with the
+# number of vectors the counters were taken at (the fourth field).
 MEASURED_TRAFFIC = {
-    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_device.h"), "d1a4878fc3822bbc", 65553550569),
-    ("k_sweep_look", "chirp_10k_409600_c128"): (("rb_look.hip", "rb_device.h"), "95969117f1d393ba", 65597510056),
-    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 32788490950),
-    ("k_sweep_c_look", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 36644102230),
+    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_device.h"), "d1a4878fc3822bbc", 1, 65553172420),
+    ("k_sweep_look", "chirp_10k_409600_c128"): (("rb_look.hip", "rb_device.h"), "95969117f1d393ba", 6, 65597149763),
+    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 1, 32788303618),
+    ("k_sweep_c_look", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "175d21ca4f2e60e9", 3, 34481006746),
 }
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, vectors=1):
     import hashlib
     rec = MEASURED_TRAFFIC.get((kernel, workload))
-    if rec is None:
+    if rec is None or rec[2] != vectors:
         return None
     m = hashlib.sha256()
     try:
@@ -70,7 +70,7 @@ def measured_traffic(kernel, workload):
             m.update(open(os.path.join(ROOT, "paper_1805_06124_amd", "csrc", f), "rb").read())
     except OSError:
         return None
-    return rec[2] if m.hexdigest()[:16] == rec[1] else None
+    return rec[3] if m.hexdigest()[:16] == rec[1] else None
 
 
 def sweep_bytes(N, M):
@@ -606,7 +606,8 @@ def main():
                     roofline={"kernel": sweep_kernel, "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "traffic": measured_traffic(sweep_kernel, w.name),
+                              "traffic": measured_traffic(sweep_kernel, w.name,
+                                                         round(v_mean) if sweep_kernel == "k_sweep_look" else 1),
                               "ms_per_launch": ms, "bytes_per_launch": by,
                               "achievable_read_GBs": read_gbs,
                               "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read_gbs},
@@ -692,7 +693,8 @@ def main():
                      roofline={"kernel": kern32, "bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "traffic": measured_traffic(kern32, w.name.replace("c128", "c64")),
+                               "traffic": measured_traffic(kern32, w.name.replace("c128", "c64"),
+                                                          round(sp["sweeps"]["vectors_per_predicting_sweep"]) if sp["look_main"] else 1),
                                "ms_per_launch": ms, "bytes_per_launch": by,
                                "achievable_read_GBs": read32,
                                "frac_of_achievable": by / (ms * 1e-3) / 1e9 / read32},

@@ -38,16 +38,22 @@ def test_agreement_summary():
 
 def test_measured_traffic_is_gated_by_source_hash():
     """Stored counter traffic is reported only for the kernel source it was
-    measured on (and never for an unknown kernel)."""
+    measured on, for launches with the number of vectors it was measured at
+    (and never for an unknown kernel)."""
     assert bench.measured_traffic("k_unknown", "chirp_10k_409600_c128") is None
     key = ("k_sweep_z", "chirp_10k_409600_c128")
-    src, h, value = bench.MEASURED_TRAFFIC[key]
+    src, h, vec, value = bench.MEASURED_TRAFFIC[key]
+    assert bench.measured_traffic(*key, vec) == value
     saved = bench.MEASURED_TRAFFIC[key]
     try:
-        bench.MEASURED_TRAFFIC[key] = (src, "0" * 16, value)
-        assert bench.measured_traffic(*key) is None
+        bench.MEASURED_TRAFFIC[key] = (src, "0" * 16, vec, value)
+        assert bench.measured_traffic(*key, vec) is None
     finally:
         bench.MEASURED_TRAFFIC[key] = saved
+    lk = ("k_sweep_c_look", "chirp_10k_409600_c64")
+    v = bench.MEASURED_TRAFFIC[lk][2]
+    assert bench.measured_traffic(*lk, v) is not None
+    assert bench.measured_traffic(*lk, v + 1) is None
 
 
 def test_bench_refuses_more_than_one_gpu():
