@@ -234,34 +234,40 @@ typedef __attribute__((address_space(1))) const void global_void32_t;
 // its coefficients c_out[v * M + j].  The vectors' rows of each 512-row tile
 // are shared by the workgroup's waves through LDS, copied by direct
 // global-to-LDS loads one tile ahead into one of two buffers, as in the FP64
-// k_sweep_look.
+// k_sweep_look.  From four vectors on the workgroup's 16 columns are spread
+// over eight waves of two columns each (half the accumulator registers per
+// lane, twice the waves per SIMD: 25.7 ms against 27.6 ms with six vectors on
+// 10,000 x 1,638,400); each column's arithmetic is the same either way.
 template <int V>
-__global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
+constexpr int look32_waves() { return V >= 4 ? 8 : kS32Waves; }
+template <int V>
+__global__ __launch_bounds__(look32_waves<V>() * 64) void k_sweep_c_look(
     const float2* __restrict__ S, int64_t N, int64_t M, int64_t ldS, const float2* __restrict__ e, int64_t ldv,
     const double* __restrict__ nrm, double* __restrict__ acc, const uint8_t* __restrict__ mask,
     double2* __restrict__ c_out, ArgMax* __restrict__ partial) {
+  constexpr int kLW = look32_waves<V>(), kLC = kS32ColsPerBlock / kLW;  // waves, columns per wave
   constexpr int kU = kS32Unroll / 2;
   constexpr int kRows = 64 * kS32Unroll;
   __shared__ __align__(16) float2 sbuf[2][V][kRows];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t col0 = (int64_t)blockIdx.x * kS32ColsPerBlock + (int64_t)wave * kS32Cols;
-  const float2* cp[kS32Cols];
+  const int64_t col0 = (int64_t)blockIdx.x * kS32ColsPerBlock + (int64_t)wave * kLC;
+  const float2* cp[kLC];
 #pragma unroll
-  for (int c = 0; c < kS32Cols; ++c) {
+  for (int c = 0; c < kLC; ++c) {
     int64_t j = col0 + c;
     if (j > M - 1) j = M - 1;
     cp[c] = S + j * ldS;
   }
-  double re[V][kS32Cols], im[V][kS32Cols];
+  double re[V][kLC], im[V][kLC];
 #pragma unroll
   for (int v = 0; v < V; ++v)
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c) re[v][c] = im[v][c] = 0.0;
+    for (int c = 0; c < kLC; ++c) re[v][c] = im[v][c] = 0.0;
   const int64_t nch = N / kRows;
   // rows [ch kRows, (ch + 1) kRows) of every vector: 64 lanes x 16 B per load
   auto fill = [&](int64_t ch, float2 (*dst)[kRows]) {
-    for (int p = wave; p < V * kU; p += kS32Waves) {
+    for (int p = wave; p < V * kU; p += kLW) {
       const int v = p / kU, u = p % kU;
       const float2* src = e + v * ldv + ch * kRows + 2 * (64 * u + lane);
       __builtin_amdgcn_global_load_lds((global_void32_t*)src, (lds_void32_t*)&dst[v][2 * 64 * u], 16, 0, 0);
@@ -269,9 +275,9 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
   };
   auto tile = [&](int64_t ch, float2 (*cur)[kRows]) {
     const int64_t base = ch * kRows;
-    f4v sv[kS32Cols][kU];
+    f4v sv[kLC][kU];
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c)
+    for (int c = 0; c < kLC; ++c)
 #pragma unroll
       for (int u = 0; u < kU; ++u)
         sv[c][u] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(cp[c] + base + 2 * (64 * u + lane)));
@@ -281,7 +287,7 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
 #pragma unroll
       for (int u = 0; u < kU; ++u) ev[u] = *reinterpret_cast<const f4v*>(&cur[v][2 * (64 * u + lane)]);
 #pragma unroll
-      for (int c = 0; c < kS32Cols; ++c) {
+      for (int c = 0; c < kLC; ++c) {
         float r32 = 0.f, i32 = 0.f;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -305,23 +311,23 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
   const int64_t nfull = nch * kRows;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    float r32[kS32Cols], i32[kS32Cols];
+    float r32[kLC], i32[kLC];
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c) r32[c] = i32[c] = 0.f;
+    for (int c = 0; c < kLC; ++c) r32[c] = i32[c] = 0.f;
     for (int64_t n = nfull + lane; n < N; n += 64) {
       const float2 ev = e[v * ldv + n];
 #pragma unroll
-      for (int c = 0; c < kS32Cols; ++c) cmac_conj32(ev, ld_stream(cp[c] + n), r32[c], i32[c]);
+      for (int c = 0; c < kLC; ++c) cmac_conj32(ev, ld_stream(cp[c] + n), r32[c], i32[c]);
     }
 #pragma unroll
-    for (int c = 0; c < kS32Cols; ++c) {
+    for (int c = 0; c < kLC; ++c) {
       re[v][c] += (double)r32[c];
       im[v][c] += (double)i32[c];
     }
   }
   __shared__ vi scand[kS32ColsPerBlock];
 #pragma unroll
-  for (int c = 0; c < kS32Cols; ++c) {
+  for (int c = 0; c < kLC; ++c) {
     const int64_t j = col0 + c;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -336,9 +342,9 @@ __global__ __launch_bounds__(kS32Waves * 64) void k_sweep_c_look(
             c_out[j] = make_double2(cr, ci);
             if (!(mask && mask[j])) cand = {nrm[j] - a, j};
           }
-          scand[wave * kS32Cols + c] = cand;
+          scand[wave * kLC + c] = cand;
         }
-      } else if (j < M && lane == c + kS32Cols * v) {
+      } else if (j < M && lane == c + kLC * v) {
         c_out[v * M + j] = make_double2(cr, ci);
       }
     }
@@ -466,7 +472,8 @@ hipError_t launch_sweep_c_look_t(const float2* S, int64_t N, int64_t M, int64_t 
                                  const double* nrm, double* acc, const uint8_t* mask, double2* c_out,
                                  ArgMax* partial, hipStream_t s) {
   const int64_t grid = (M + kS32ColsPerBlock - 1) / kS32ColsPerBlock;
-  hipLaunchKernelGGL(k_sweep_c_look<V>, dim3((unsigned)grid), dim3(kS32Waves * 64), 0, s, S, N, M, ldS, e, ldv, nrm,
+  hipLaunchKernelGGL(k_sweep_c_look<V>, dim3((unsigned)grid), dim3(look32_waves<V>() * 64), 0, s, S, N, M, ldS, e,
+                     ldv, nrm,
                      acc, mask, c_out, partial);
   return hipGetLastError();
 }
