@@ -491,14 +491,25 @@ int rb_enrich_z(rb_regen_fn regen, void *regen_ctx, int64_t N, int64_t Mv, int64
  *   Vout   device, complex128 j x j (ld j): the left singular vectors of C
  *          in the same order, or NULL (out)
  *   k_out  host: k (out)
- * Workspace: about 16 (j M + 5 j^2) bytes, 16 KB of partial Gram tiles
- * per (32-row tile pair, split) and, for j <= 141, a rotation log of
- * 60 (j + 1)^2 / 2 x 32 bytes.  Returns RB_ENOCONV if a Jacobi solve does
- * not settle within 60 sweeps.
+ *   ws, ws_bytes  device workspace of at least
+ *          rb_reconstruct_z_workspace(j, M) bytes (about 16 (j M + 5 j^2)
+ *          bytes, 16 KB of partial Gram tiles per (32-row tile pair, split)
+ *          and, for j <= 141, a rotation log of 60 (j + 1)^2 / 2 x 32
+ *          bytes), 256-byte aligned (else RB_EINVAL); caller-owned,
+ *          contents undefined on return.  ws == NULL: the call allocates and
+ *          frees it itself.  A smaller ws_bytes returns RB_ENOMEM.
+ * Returns RB_ENOCONV if a Jacobi solve does not settle within 60 sweeps.
  */
 int rb_reconstruct_z(const void *E, int64_t N, int64_t j, int64_t ldE, const void *C, int64_t M, int64_t ldC,
-                     double tau2, void *X, int64_t ldX, double *sigma, void *Vout, int64_t *k_out,
-                     hipStream_t stream);
+                     double tau2, void *X, int64_t ldX, double *sigma, void *Vout, int64_t *k_out, void *ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/*
+ * rb_reconstruct_z_workspace -- device workspace bytes rb_reconstruct_z
+ * needs for j basis vectors and M columns of C; 0 for sizes it rejects
+ * (j < 1, j > 2048, M < 1).
+ */
+size_t rb_reconstruct_z_workspace(int64_t j, int64_t M);
 
 /*
  * rb_eim_z -- empirical-interpolation (EI) nodes of the basis e_1..e_k

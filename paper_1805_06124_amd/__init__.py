@@ -60,7 +60,8 @@ EXPORTS = ["rb_default_opts", "rb_strerror", "rb_last_error", "rb_colnorms_z", "
            "rb_sweep_c", "rb_greedy_c", "rb_chirp_table", "rb_chirp_regen", "rb_project_z", "rb_chirp_fill",
            "rb_mlp_param_count", "rb_mlp_workspace_bytes", "rb_mlp_forward", "rb_mlp_loss", "rb_mlp_backward",
            "rb_mlp_adam", "rb_mlp_gather", "rb_coef_targets", "rb_coef_relerr", "rb_greedy_resume_z",
-           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_eim_z", "rb_eim_errors_z",
+           "rb_residual_norms_z", "rb_enrich_z", "rb_reconstruct_z", "rb_reconstruct_z_workspace", "rb_eim_z",
+           "rb_eim_errors_z",
            "rb_chirp_params", "rb_stream_read", "rb_greedy_z_workspace", "rb_greedy_c_workspace",
            "rb_greedy_z_noalloc", "rb_mlp_phase_features", "rb_mlp_train", "rb_mlp_train_workspace_bytes"]
 
@@ -107,7 +108,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rb_enrich_z.argtypes = [P, P, I64, I64, I64, D, I64, P, I64, I64, P, P, P, P, ctypes.POINTER(I64), P, P, P,
                               ctypes.POINTER(Opts), ctypes.POINTER(Stats), P]
     L.rb_reconstruct_z.restype = ctypes.c_int
-    L.rb_reconstruct_z.argtypes = [P, I64, I64, I64, P, I64, I64, D, P, I64, P, P, ctypes.POINTER(I64), P]
+    L.rb_reconstruct_z.argtypes = [P, I64, I64, I64, P, I64, I64, D, P, I64, P, P, ctypes.POINTER(I64), P,
+                                   ctypes.c_size_t, P]
+    L.rb_reconstruct_z_workspace.restype = ctypes.c_size_t
+    L.rb_reconstruct_z_workspace.argtypes = [I64, I64]
     L.rb_eim_z.restype = ctypes.c_int
     L.rb_eim_z.argtypes = [P, I64, I64, I64, P, P, P, P, ctypes.POINTER(I64), P]
     L.rb_eim_errors_z.restype = ctypes.c_int
@@ -504,12 +508,21 @@ def project(E: torch.Tensor, S: torch.Tensor, stream=None) -> torch.Tensor:
     return C
 
 
-def reconstruct(E: torch.Tensor, C: torch.Tensor, tau2: float, want_v: bool = False, stream=None) -> dict:
+def reconstruct_workspace_bytes(j: int, M: int) -> int:
+    """Device workspace bytes of reconstruct() for j basis vectors and M
+    coefficient columns (0 if the sizes are rejected)."""
+    return int(load().rb_reconstruct_z_workspace(int(j), int(M)))
+
+
+def reconstruct(E: torch.Tensor, C: torch.Tensor, tau2: float, want_v: bool = False, stream=None,
+                ws: torch.Tensor | None = None) -> dict:
     """Alg. 4 from the greedy basis E (j, N) and its coefficients C = E^H S
     as returned by project() ((M, j): row m holds the coefficients of s_m).
-    Returns dict with X ((k, N) complex128 on the GPU, row i = x_{i+1}),
-    sigma (numpy (j,), non-increasing), k, and V ((j, j) on the GPU,
-    column i = left singular vector i of C) if want_v."""
+    ws: optional uint8 GPU workspace of reconstruct_workspace_bytes(j, M)
+    bytes; by default one is taken from torch's allocator (so repeated calls
+    reuse its cached memory).  Returns dict with X ((k, N) complex128 on the
+    GPU, row i = x_{i+1}), sigma (numpy (j,), non-increasing), k, and V
+    ((j, j) on the GPU, column i = left singular vector i of C) if want_v."""
     import numpy as np
     j, N, ldE = _mat(E, torch.complex128)
     M, j2, ldC = _mat(C, torch.complex128)
@@ -517,11 +530,15 @@ def reconstruct(E: torch.Tensor, C: torch.Tensor, tau2: float, want_v: bool = Fa
         raise ValueError("C must have one coefficient per basis vector")
     X = torch.empty((j, N), dtype=torch.complex128, device=E.device)
     V = torch.empty((j, j), dtype=torch.complex128, device=E.device) if want_v else None
+    if ws is None:
+        nbytes = reconstruct_workspace_bytes(j, M)
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=E.device)
+    ptr, nws = _ws(ws)
     sigma = np.zeros(j)
     kout = ctypes.c_int64()
     _check("rb_reconstruct_z", load().rb_reconstruct_z(_ptr(E), N, j, ldE, _ptr(C), M, ldC, float(tau2), _ptr(X),
                                                        N, sigma.ctypes.data_as(ctypes.c_void_p), _ptr(V),
-                                                       ctypes.byref(kout), _stream(stream)))
+                                                       ctypes.byref(kout), ptr, nws, _stream(stream)))
     k = kout.value
     # V was written column-major j x j: the tensor's row i is column i
     return dict(X=X[:k], sigma=sigma, k=k, V=(V.T if V is not None else None))

@@ -674,54 +674,89 @@ static hipError_t gemm_nn(const double2* A, int64_t lda, const double2* B, int64
 
 }  // namespace rb
 
-extern "C" {
+// The reconstruction's device buffers, carved from one workspace (the same
+// sequence of take() calls sizes it and lays it out).
+struct ReconBufs {
+  double2 *P, *G, *V0, *V1, *V, *B;
+  double* sig;
+  int64_t* perm;
+  int* info;
+  double4* rot;
+};
+constexpr double kReconEps = 4.0 * 0x1p-53;
+constexpr int kReconSweeps = 60;
 
-int rb_reconstruct_z(const void* E_, int64_t N, int64_t j, int64_t ldE, const void* C_, int64_t M, int64_t ldC,
-                     double tau2, void* X_, int64_t ldX, double* sigma, void* Vout, int64_t* k_out,
-                     hipStream_t stream) {
-  last_error().clear();
-  if (!E_ || !C_ || !X_ || !sigma || !k_out || N <= 0 || j <= 0 || M <= 0 || j > N || j > 2 * kMaxPairs ||
-      !valid_ld(N, ldE) || ldC < j || !valid_ld(N, ldX) || !(tau2 >= 0.0) || !std::isfinite(tau2))
-    return set_error(RB_EINVAL, "rb_reconstruct_z: bad arguments");
-  const double2* E = static_cast<const double2*>(E_);
-  const double2* C = static_cast<const double2*>(C_);
-  double2* X = static_cast<double2*>(X_);
+static bool recon_sizes_ok(int64_t j, int64_t M) { return j >= 1 && j <= 2 * kMaxPairs && M >= 1; }
+
+static size_t recon_carve(void* base, int64_t j, int64_t M, ReconBufs& b) {
   const int ntile = (int)((j + kGT - 1) / kGT);
   const int ntp = ntile * (ntile + 1) / 2;
   const int ns = gram_splits(j, M);
   const size_t jj = (size_t)j * (size_t)j;
+  Carve c(base);
+  b.P = c.take<double2>((size_t)ns * ntp * kGT * kGT);
+  b.G = c.take<double2>(jj);
+  b.V0 = c.take<double2>(jj);
+  b.V1 = c.take<double2>(jj);
+  b.V = c.take<double2>(jj);
+  b.B = c.take<double2>((size_t)j * (size_t)M);
+  b.sig = c.take<double>(j);
+  b.perm = c.take<int64_t>(j);
+  b.info = c.take<int>(2);
+  const size_t nrot = jacobi_log_count(j, kReconSweeps);
+  b.rot = nrot ? c.take<double4>(nrot) : nullptr;
+  return c.used;
+}
 
-  const double eps = 4.0 * 0x1p-53;
-  const int max_sweeps = 60;
-  DevBuf P, G, V0, V1, V, B, d_sig, d_perm, d_info, d_rot;
-  RB_ALLOC(P, sizeof(double2) * (size_t)ns * ntp * kGT * kGT);
-  RB_ALLOC(G, sizeof(double2) * jj);
-  RB_ALLOC(V0, sizeof(double2) * jj);
-  RB_ALLOC(V1, sizeof(double2) * jj);
-  RB_ALLOC(V, sizeof(double2) * jj);
-  RB_ALLOC(B, sizeof(double2) * (size_t)j * (size_t)M);
-  RB_ALLOC(d_sig, sizeof(double) * j);
-  RB_ALLOC(d_perm, sizeof(int64_t) * j);
-  RB_ALLOC(d_info, sizeof(int) * 2);
-  const size_t nrot = jacobi_log_count(j, max_sweeps);
-  if (nrot) RB_ALLOC(d_rot, sizeof(double4) * nrot);
-  double4* rot = static_cast<double4*>(d_rot.p);
+extern "C" {
+
+size_t rb_reconstruct_z_workspace(int64_t j, int64_t M) {
+  if (!recon_sizes_ok(j, M)) return 0;
+  ReconBufs b;
+  return recon_carve(nullptr, j, M, b);
+}
+
+int rb_reconstruct_z(const void* E_, int64_t N, int64_t j, int64_t ldE, const void* C_, int64_t M, int64_t ldC,
+                     double tau2, void* X_, int64_t ldX, double* sigma, void* Vout, int64_t* k_out, void* ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  last_error().clear();
+  if (!E_ || !C_ || !X_ || !sigma || !k_out || N <= 0 || !recon_sizes_ok(j, M) || j > N || !valid_ld(N, ldE) ||
+      ldC < j || !valid_ld(N, ldX) || !(tau2 >= 0.0) || !std::isfinite(tau2))
+    return set_error(RB_EINVAL, "rb_reconstruct_z: bad arguments");
+  const double2* E = static_cast<const double2*>(E_);
+  const double2* C = static_cast<const double2*>(C_);
+  double2* X = static_cast<double2*>(X_);
+  const int ns = gram_splits(j, M);
+  const size_t jj = (size_t)j * (size_t)j;
+
+  ReconBufs b;
+  const size_t need = recon_carve(nullptr, j, M, b);
+  DevBuf own;
+  if (ws) {
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+      return set_error(RB_EINVAL, "rb_reconstruct_z: workspace not 256-byte aligned");
+    if (ws_bytes < need)
+      return set_error(RB_ENOMEM, "rb_reconstruct_z: workspace of %zu bytes, %zu needed", ws_bytes, need);
+  } else {
+    RB_ALLOC(own, need);
+    ws = own.p;
+  }
+  recon_carve(ws, j, M, b);
 
   // 1. G = C C^H and its Jacobi eigenvectors V0
-  RB_HIP(gram(C, j, M, ldC, P.as<double2>(), ns, G.as<double2>(), stream));
-  RB_HIP(jacobi(G.as<double2>(), j, V0.as<double2>(), rot, max_sweeps, eps, d_info.as<int>(), stream));
+  RB_HIP(gram(C, j, M, ldC, b.P, ns, b.G, stream));
+  RB_HIP(jacobi(b.G, j, b.V0, b.rot, kReconSweeps, kReconEps, b.info, stream));
   // 2. refinement: B = V0^H C, G2 = B B^H, Jacobi -> V1, lambda
-  RB_HIP(launch_project_z(V0.as<double2>(), j, j, j, C, M, ldC, B.as<double2>(), j, stream));
-  RB_HIP(gram(B.as<double2>(), j, M, j, P.as<double2>(), ns, G.as<double2>(), stream));
-  RB_HIP(jacobi(G.as<double2>(), j, V1.as<double2>(), rot, max_sweeps, eps, d_info.as<int>() + 1, stream));
+  RB_HIP(launch_project_z(b.V0, j, j, j, C, M, ldC, b.B, j, stream));
+  RB_HIP(gram(b.B, j, M, j, b.P, ns, b.G, stream));
+  RB_HIP(jacobi(b.G, j, b.V1, b.rot, kReconSweeps, kReconEps, b.info + 1, stream));
   // 3. V = V0 V1, ordered by descending eigenvalue
-  RB_HIP(gemm_nn(V0.as<double2>(), j, V1.as<double2>(), j, j, j, j, V.as<double2>(), j, stream));
-  hipLaunchKernelGGL(k_eig_order, dim3((unsigned)((j + 255) / 256)), dim3(256), 0, stream, G.as<double2>(), j,
-                     d_sig.as<double>(), d_perm.as<int64_t>());
+  RB_HIP(gemm_nn(b.V0, j, b.V1, j, j, j, j, b.V, j, stream));
+  hipLaunchKernelGGL(k_eig_order, dim3((unsigned)((j + 255) / 256)), dim3(256), 0, stream, b.G, j, b.sig, b.perm);
   RB_HIP(hipGetLastError());
   int info[2];
-  RB_HIP(hipMemcpyAsync(info, d_info.p, sizeof info, hipMemcpyDeviceToHost, stream));
-  RB_HIP(hipMemcpyAsync(sigma, d_sig.p, sizeof(double) * j, hipMemcpyDeviceToHost, stream));
+  RB_HIP(hipMemcpyAsync(info, b.info, sizeof info, hipMemcpyDeviceToHost, stream));
+  RB_HIP(hipMemcpyAsync(sigma, b.sig, sizeof(double) * j, hipMemcpyDeviceToHost, stream));
   RB_HIP(hipStreamSynchronize(stream));
   if (info[0] < 0 || info[1] < 0) return set_error(RB_ENOCONV, "rb_reconstruct_z: Jacobi did not converge");
   for (int64_t i = 0; i < j; ++i)
@@ -729,9 +764,9 @@ int rb_reconstruct_z(const void* E_, int64_t N, int64_t j, int64_t ldE, const vo
   // 4. k = #{sigma_i >= tau2}; X_k = E V(:, 1:k)
   int64_t k = 0;
   while (k < j && sigma[k] >= tau2) ++k;
-  double2* Vs = Vout ? static_cast<double2*>(Vout) : V1.as<double2>();  // V1 is free now
-  hipLaunchKernelGGL(k_permute_cols, dim3((unsigned)((jj + 255) / 256)), dim3(256), 0, stream, V.as<double2>(), j,
-                     j, d_perm.as<int64_t>(), j, Vs, j);
+  double2* Vs = Vout ? static_cast<double2*>(Vout) : b.V1;  // V1 is free now
+  hipLaunchKernelGGL(k_permute_cols, dim3((unsigned)((jj + 255) / 256)), dim3(256), 0, stream, b.V, j, j, b.perm, j,
+                     Vs, j);
   RB_HIP(hipGetLastError());
   RB_HIP(gemm_nn(E, ldE, Vs, j, N, k, j, X, ldX, stream));
   RB_HIP(hipStreamSynchronize(stream));

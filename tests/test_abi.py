@@ -176,3 +176,34 @@ def test_greedy_workspace_contract_on_host(L):
                        err.ctypes.data_as(P), rho.ctypes.data_as(P), None, ctypes.byref(kk), P(4096), needc - 1,
                        None, None, None)
     assert rc == -2 and kk.value == -7
+
+
+def test_reconstruct_workspace_contract_on_host(L):
+    """rb_reconstruct_z_workspace grows with j and M and rejects sizes the
+    routine rejects; with a caller workspace, too small -> RB_ENOMEM and
+    misaligned -> RB_EINVAL, before any device work (the pointers here are
+    not device memory)."""
+    z = L.rb_reconstruct_z_workspace(141, 409600)
+    assert z >= 16 * (141 * 409600 + 5 * 141 * 141)
+    assert L.rb_reconstruct_z_workspace(141, 409601) > z
+    assert L.rb_reconstruct_z_workspace(140, 409600) < z
+    # j > 141: the global-memory Jacobi, no rotation log
+    assert L.rb_reconstruct_z_workspace(142, 409600) < z
+    for j, M in ((0, 10), (2049, 10), (5, 0), (-1, 10)):
+        assert L.rb_reconstruct_z_workspace(j, M) == 0, (j, M)
+    assert L.rb_reconstruct_z_workspace(2048, 10) > 0
+    import numpy as np
+    P = ctypes.c_void_p
+    need = L.rb_reconstruct_z_workspace(3, 10)
+    sigma = np.zeros(3)
+
+    def call(ws, nbytes, j=3):
+        k = ctypes.c_int64(-7)
+        rc = L.rb_reconstruct_z(P(1), 8, j, 8, P(1), 10, 3, 0.0, P(1), 8, sigma.ctypes.data_as(P), None,
+                                ctypes.byref(k), P(ws) if ws else None, nbytes, None)
+        return rc, k.value
+
+    assert call(4096, need - 1) == (-2, -7)
+    assert b"needed" in L.rb_last_error()
+    assert call(4096 + 16, need) == (-1, -7)
+    assert call(4096, need, j=0) == (-1, -7)

@@ -146,3 +146,26 @@ def test_reconstruct_edges(rb):
     assert np.linalg.norm(V.conj().T @ V - np.eye(30), 2) <= 1e-13
     got = _run(rb, g["E"], C, 1e9)
     assert got["k"] == 0 and got["X"].shape[0] == 0
+
+
+def test_reconstruct_caller_workspace(rb):
+    """A caller workspace gives the same bits as the library's own, on two
+    calls in a row sharing it (the second smaller); an undersized one is
+    refused with RB_ENOMEM."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    S = oracle.chirp(w.params(), w.N, w.flo, w.fhi)
+    g = oracle.greedy(S, w.tol, w.kmax)
+    C = oracle.project(g["E"], S)
+    E, Ct = _dev(g["E"]), _dev(C.T)
+    j, M = E.shape[0], Ct.shape[0]
+    ws = torch.empty(rb.reconstruct_workspace_bytes(j, M), dtype=torch.uint8, device="cuda")
+    ws.fill_(0xFF)
+    for jj in (j, j - 7):
+        ref = rb.reconstruct(E[:jj].contiguous(), Ct[:, :jj].contiguous(), 1e-6, want_v=True)
+        got = rb.reconstruct(E[:jj].contiguous(), Ct[:, :jj].contiguous(), 1e-6, want_v=True, ws=ws)
+        assert got["k"] == ref["k"]
+        assert np.array_equal(got["sigma"], ref["sigma"])
+        assert torch.equal(got["X"], ref["X"]) and torch.equal(got["V"], ref["V"])
+    small = torch.empty(rb.reconstruct_workspace_bytes(j, M) - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rb.RBError):
+        rb.reconstruct(E, Ct, 1e-6, ws=small)
