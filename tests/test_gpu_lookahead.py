@@ -111,6 +111,20 @@ def test_lookahead_many_columns(rb):
     assert g1["k"] > 20 and g1["stats"]["look_steps"] > 0
 
 
+@pytest.mark.parametrize("look", [3, 5])
+def test_mixed_lookahead_ragged_columns(rb, look):
+    """A column count that is not a multiple of a workgroup's 16 columns
+    (1,995 of the small chirp family) with depths whose sweeps spread the
+    16 columns over eight waves of two: bit-identical to no lookahead."""
+    w = ri.WORKLOADS["chirp_small_c128"]
+    P = _dev(w.params(M=1995))
+    S32 = rb.chirp_fill(P, w.N, w.flo, w.fhi, dtype=torch.complex64)
+    g0 = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=torch.empty_like(S32), lookahead32=0)
+    g1 = rb.greedy_c(S32, w.tol, w.kmax, P, w.flo, w.fhi, W=torch.empty_like(S32), lookahead32=look)
+    _same(g0, g1)
+    assert g1["stats"]["look_steps"] > 0 and g1["k"] > 20
+
+
 @pytest.mark.parametrize("kw", [dict(), dict(lookahead32=1), dict(lookahead32=5), dict(anchor_max=6, lookahead32=4),
                                 dict(lookahead32=2, look_k=3)])
 def test_mixed_lookahead_bit_identical(rb, kw):
