@@ -449,9 +449,12 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   // once, a predicted one (rb_look.hip) not at all, and both run the same
   // kernels.  jsrc (device) or jhost names the column; prev chains
   // predictions; an accepted vector goes to E[:, kk].
-  auto gs_launch = [&](const ArgMax* jsrc, int64_t jhost, const GsState* prev, int64_t kk, GsState* gs) -> int {
+  // passes: how many passes to queue (at most nu_max); an orthogonalisation
+  // that would need more is not accepted.
+  auto gs_launch = [&](const ArgMax* jsrc, int64_t jhost, const GsState* prev, int64_t kk, GsState* gs,
+                       int passes) -> int {
     RB_HIP(launch_gs_begin(X, ldX, N, jsrc, jhost, prev, nrm0, v, sq + 1, gs, stream));
-    for (int p = 0; p < o.nu_max; ++p)
+    for (int p = 0; p < passes; ++p)
       RB_HIP(launch_gs_pass(E, ldE, kk, v, N, g_coef, sq, gs, o.nu_min, o.nu_max, o.kappa, stream));
     RB_HIP(launch_gs_finish(gs, tol, sq, v, N, E + kk * ldE, stream));
     return RB_OK;
@@ -462,6 +465,11 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
   // vector in turn), orthogonalised into E[:, k + d] as its own step would
   // do it; a prediction that step would not accept ends the chain.  No
   // host round trip: the outcomes are read back with the sweep's argmax.
+  // A predicted orthogonalisation queues at most kLookPasses passes (with
+  // kappa = 2 a pivot's orthogonalisation settles after one or two: every
+  // step of the 10,000 x 409,600 chirp run does); one that needs more ends
+  // the chain and its step runs its own.
+  const int look_passes = std::min(o.nu_max, std::max(o.nu_min, kLookPasses));
   auto predict = [&](int dmax) -> int {
     tm.start();
     if (!fine_part) RB_HIP(launch_est_apply(nrm, acc, mask, nullptr, M, part, np, stream));
@@ -470,7 +478,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
       GsState* gd = z.gst + 1 + d;
       RB_HIP(launch_rerank(X, N, ldX, E + (k - 1 + d) * ldE, z.list, look_k, nrm, acc, z.acc_l, d == 0 ? 1 : 0,
                            mask, z.gst + 1, d, z.rpart, z.lres, stream));
-      int rc = gs_launch(z.lres, -1, d > 0 ? gd - 1 : nullptr, k + d, gd);
+      int rc = gs_launch(z.lres, -1, d > 0 ? gd - 1 : nullptr, k + d, gd, look_passes);
       if (rc != RB_OK) return rc;
     }
     lap(tm, &st.ms_look, nullptr);
@@ -533,7 +541,7 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
         }
         RB_HIP(launch_scale_into(v, N, nrm + J, E, stream));
       } else {
-        int rc = gs_launch(nullptr, J, nullptr, k, z.gst);
+        int rc = gs_launch(nullptr, J, nullptr, k, z.gst, o.nu_max);
         if (rc != RB_OK) return rc;
         RB_HIP(hipMemcpyAsync(h_gs, z.gst, sizeof(GsState), hipMemcpyDeviceToHost, stream));
         RB_HIP(hipStreamSynchronize(stream));

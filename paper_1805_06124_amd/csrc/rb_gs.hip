@@ -230,30 +230,52 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_begin(const double2* __restri
     st->before = st->after = 0.0;
   }
 }
-// ||v|| before the first pass, from sq1 = ||v||^2
-__global__ void k_gs_setup(const double* __restrict__ sq1, GsState* __restrict__ st) {
-  if (!st->live) return;
-  st->before = st->after = sqrt(sq1[0]);
-}
-// After a pass (sq = ||v||^2): Hoffmann's criterion decides whether another
-// pass is due (Sec. 6.1.2), exactly as a host loop over the passes would.
-__global__ void k_gs_check(const double* __restrict__ sq, GsState* __restrict__ st, int nu_min, int nu_max,
-                           double kappa) {
+// ||v||^2 into sq[0] (k_sqnorms_small's sum, one vector) and, from it, the
+// state: with check == 0 the norm before the first pass; otherwise the
+// verdict after a pass, Hoffmann's criterion deciding whether another pass
+// is due (Sec. 6.1.2), exactly as a host loop over the passes would.
+// Nothing happens once the orthogonalisation is done (or was never live).
+__global__ __launch_bounds__(1024) void k_gs_norm(const double2* __restrict__ v, int64_t N, double* __restrict__ sq,
+                                                  GsState* __restrict__ st, int check, int nu_min, int nu_max,
+                                                  double kappa) {
   if (st->done) return;
-  const double after = sqrt(sq[0]);
-  st->passes += 1;
-  st->after = after;
-  if (st->passes >= nu_min && after > st->before / kappa) {
-    st->settled = 1;
-    st->done = 1;
-  } else {
-    st->before = after;
-    if (st->passes >= nu_max) st->done = 1;
+  dd s = {0.0, 0.0};
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
+    double2 a = v[n];
+    dd_add_sq(s, a.x);
+    dd_add_sq(s, a.y);
+  }
+  s = wave_dd_sum(s);
+  __shared__ dd sh[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd t = sh[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) t = dd_add(t, sh[w]);
+    const double q = t.hi + t.lo;
+    sq[0] = q;
+    const double r = sqrt(q);
+    if (!check) {
+      st->before = st->after = r;
+      return;
+    }
+    st->passes += 1;
+    st->after = r;
+    if (st->passes >= nu_min && r > st->before / kappa) {
+      st->settled = 1;
+      st->done = 1;
+    } else {
+      st->before = r;
+      if (st->passes >= nu_max) st->done = 1;
+    }
   }
 }
 // The outcome: finite, numerically in span(E) (||v|| <= 64 u ||s_J||), and
-// accepted (live, finite, not in the span, settled unless ||v|| < tol);
-// an accepted vector is written as e = v / ||v|| into out.
+// accepted (live, finished, finite, not in the span, settled unless
+// ||v|| < tol); an accepted vector is written as e = v / ||v|| into out.
+// "Finished": settled, or nu_max passes run; a chain queued with fewer
+// passes than nu_max is not accepted when it still needed more.
 __global__ __launch_bounds__(kGsThreads) void k_gs_finish(GsState* __restrict__ st, double tol,
                                                           const double* __restrict__ sq,
                                                           const double2* __restrict__ v, int64_t N,
@@ -261,7 +283,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_finish(GsState* __restrict__ 
   const double r = st->after;
   const bool finite = __builtin_isfinite(r);
   const bool in_span = !(r > 64.0 * 0x1p-53 * sqrt(st->s_norm2));
-  const bool ok = st->live && finite && !in_span && (st->settled || r < tol);
+  const bool ok = st->live && st->done && finite && !in_span && (st->settled || r < tol);
   const int64_t n = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
   if (ok && n < N) {
     const double rr = sqrt(sq[0]);
@@ -286,10 +308,7 @@ hipError_t launch_gs_begin(const double2* X, int64_t ldX, int64_t N, const ArgMa
                      st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sqnorms_small, dim3(1), dim3(1024), 0, s, v, N, N, sq1, &st->done);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gs_setup, dim3(1), dim3(1), 0, s, sq1, st);
+  hipLaunchKernelGGL(k_gs_norm, dim3(1), dim3(1024), 0, s, v, N, sq1, st, 0, 0, 0, 0.0);
   return hipGetLastError();
 }
 
@@ -304,10 +323,7 @@ hipError_t launch_gs_pass(const double2* E, int64_t ldE, int64_t kk, double2* v,
                      1, N, skip);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sqnorms_small, dim3(1), dim3(1024), 0, s, v, N, N, sq, skip);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(1), 0, s, sq, st, nu_min, nu_max, kappa);
+  hipLaunchKernelGGL(k_gs_norm, dim3(1), dim3(1024), 0, s, v, N, sq, st, 1, nu_min, nu_max, kappa);
   return hipGetLastError();
 }
 

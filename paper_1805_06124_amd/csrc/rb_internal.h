@@ -55,6 +55,7 @@ hipError_t launch_argmax_records(const ArgMax* partial, int64_t n, ArgMax* resul
 //     partial holds rerank_partials(K) records.
 constexpr int kPivotGroup = 16;
 constexpr int kLookMax = 5;
+constexpr int kLookPasses = 2;  // Gram-Schmidt passes queued for a predicted pivot
 constexpr int kLookListMax = 8192;
 hipError_t launch_sweep_look(const double2* S, int64_t N, int64_t M, int64_t ldS, const double2* E, int64_t ldE,
                              int V, const double* nrm, double* acc, const uint8_t* mask, double2* c_out,

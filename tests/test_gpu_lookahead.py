@@ -90,6 +90,25 @@ def test_lookahead_gaussian_and_kmax(rb):
         assert g1["k"] == kmax
 
 
+def test_lookahead_two_pass_predictions_rank_and_graded(rb, chirp_small):
+    """A predicted pivot's orthogonalisation queues only two passes (one
+    that would need more is not accepted and its step runs its own).  Runs
+    into the numerical rank (exactly low-rank inputs, tol 0), a strongly
+    graded matrix and kappa squeezed towards 1 on full-rank columns stay
+    bit-identical to no lookahead, rank detection included.  (On these
+    inputs every orthogonalisation settles within two passes: a second pass
+    changes ||v|| only at second order.)"""
+    w, S = chirp_small
+    cases = [(_dev(ri.low_rank(31 + r, 400, 600, r)), 0.0, r + 12, {}) for r in (10, 40)]
+    cases.append((_dev(ri.graded(7, 300, 500, 0.7)), 0.0, 200, {}))
+    cases += [(S, w.tol, w.kmax, dict(kappa=1.0 + 2.0 ** -52))]
+    for Sx, tol, kmax, kw in cases:
+        g0 = rb.greedy(Sx, tol, kmax, check=False, lookahead=0, **kw)
+        g1 = rb.greedy(Sx, tol, kmax, check=False, lookahead=5, **kw)
+        _same(g0, g1)
+        assert g0["k"] == 0 or int(np.max(g0["nu"][:g0["k"]])) <= 2
+
+
 def test_lookahead_breakdown(rb):
     theta, delta, n = 1.3, 1e-3, 80
     S = _dev(ri.kahan(n, theta, delta))
