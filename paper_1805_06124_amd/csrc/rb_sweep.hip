@@ -158,11 +158,20 @@ __global__ __launch_bounds__(256) void k_est_argmax(const double* __restrict__ n
 // Final reduction of n partial argmax records into *result (one workgroup).
 __global__ __launch_bounds__(1024) void k_argmax_final(const ArgMax* __restrict__ partial, int64_t n,
                                                        ArgMax* __restrict__ result) {
+  // eight records per thread in flight (vi_max is a total order, so the
+  // grouping does not change the result)
+  constexpr int kU = 8;
+  const int64_t step = blockDim.x;
   vi best = {0.0, -1};
-  for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
-    vi cand = {partial[t].v, partial[t].i};
-    best = vi_max(best, cand);
+  int64_t t = threadIdx.x;
+  for (; t + (kU - 1) * step < n; t += kU * step) {
+    vi c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) c[u] = vi{partial[t + u * step].v, partial[t + u * step].i};
+#pragma unroll
+    for (int u = 0; u < kU; ++u) best = vi_max(best, c[u]);
   }
+  for (; t < n; t += step) best = vi_max(best, vi{partial[t].v, partial[t].i});
   best = wave_vi_max(best);
   __shared__ vi sbest[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
