@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_begin(const double2* __restri
 }
 // ||v||^2 into sq[0] (k_sqnorms_small's sum, one vector) and, from it, the
 // state: with check == 0 the norm before the first pass; otherwise the
-// verdict after a pass, Hoffmann's criterion deciding whether another pass
+// outcome of a pass, Hoffmann's criterion deciding whether another pass
 // is due (Sec. 6.1.2), exactly as a host loop over the passes would.
 // Nothing happens once the orthogonalisation is done (or was never live).
 __global__ __launch_bounds__(1024) void k_gs_norm(const double2* __restrict__ v, int64_t N, double* __restrict__ sq,
