@@ -169,3 +169,15 @@ def test_reconstruct_caller_workspace(rb):
     small = torch.empty(rb.reconstruct_workspace_bytes(j, M) - 1, dtype=torch.uint8, device="cuda")
     with pytest.raises(rb.RBError):
         rb.reconstruct(E, Ct, 1e-6, ws=small)
+    # ws == NULL: the library allocates its own, same bits
+    import ctypes
+    X = torch.empty((j, N := E.shape[1]), dtype=torch.complex128, device="cuda")
+    sig = np.zeros(j)
+    kk = ctypes.c_int64()
+    rc = rb.load().rb_reconstruct_z(ctypes.c_void_p(E.data_ptr()), N, j, N, ctypes.c_void_p(Ct.data_ptr()), M, j,
+                                    1e-6, ctypes.c_void_p(X.data_ptr()), N, sig.ctypes.data_as(ctypes.c_void_p),
+                                    None, ctypes.byref(kk), None, 0, None)
+    torch.cuda.synchronize()
+    ref = rb.reconstruct(E, Ct, 1e-6)
+    assert rc == 0 and kk.value == ref["k"]
+    assert np.array_equal(sig, ref["sigma"]) and torch.equal(X[:kk.value], ref["X"])
