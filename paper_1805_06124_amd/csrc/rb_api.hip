@@ -541,10 +541,19 @@ int greedy_z_core(const char* fn, const void* S_, int64_t N, int64_t M, int64_t 
         }
         RB_HIP(launch_scale_into(v, N, nrm + J, E, stream));
       } else {
-        int rc = gs_launch(nullptr, J, nullptr, k, z.gst, o.nu_max);
+        // the passes a pivot usually needs first; the rest only if it has not
+        // finished (they continue from the device state)
+        int rc = gs_launch(nullptr, J, nullptr, k, z.gst, look_passes);
         if (rc != RB_OK) return rc;
         RB_HIP(hipMemcpyAsync(h_gs, z.gst, sizeof(GsState), hipMemcpyDeviceToHost, stream));
         RB_HIP(hipStreamSynchronize(stream));
+        if (!h_gs->done) {
+          for (int p = look_passes; p < o.nu_max; ++p)
+            RB_HIP(launch_gs_pass(E, ldE, k, v, N, g_coef, sq, z.gst, o.nu_min, o.nu_max, o.kappa, stream));
+          RB_HIP(launch_gs_finish(z.gst, tol, sq, v, N, E + k * ldE, stream));
+          RB_HIP(hipMemcpyAsync(h_gs, z.gst, sizeof(GsState), hipMemcpyDeviceToHost, stream));
+          RB_HIP(hipStreamSynchronize(stream));
+        }
         const GsState& g = *h_gs;
         r = g.after;
         passes = g.passes;
