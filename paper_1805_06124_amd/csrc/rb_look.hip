@@ -190,7 +190,10 @@ __global__ __launch_bounds__(256) void k_est_apply(const double* __restrict__ nr
 // key: eight rounds of 8-bit histograms find the K-th record's key; records
 // above it all enter the list, records equal to it fill the remaining places
 // in index order.  (Fewer rounds would not do: early in a run the best
-// thousands of estimates agree to 1e-4.)  The keys are read once, thread t
+// thousands of estimates agree to 1e-4.)  Each wave counts into its own
+// histogram (most keys share their leading bytes, so one shared histogram
+// would serialise the atomics), and one wave sums them and finds the K-th
+// key's bin with a prefix sum over lanes.  The keys are read once, thread t
 // taking records t, t + 1024, ..., and kept in registers.  The list's order
 // is free (the reranking is order-independent), so records above the K-th
 // key take places from an LDS counter; only when the records equal to it
@@ -233,7 +236,7 @@ __device__ __forceinline__ int block_exscan(int x, int* swave, int* total) {
 }
 __global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restrict__ in, int64_t n, int K,
                                                             ArgMax* __restrict__ list) {
-  __shared__ unsigned hist[256];
+  __shared__ unsigned hist[kSelThreads / 64][256];  // one histogram per wave (fewer colliding atomics)
   __shared__ uint64_t s_prefix;
   __shared__ int s_above, s_all, s_na, s_nb;
   __shared__ int swave[kSelThreads / 64 + 1];
@@ -245,27 +248,47 @@ __global__ __launch_bounds__(kSelThreads) void k_look_list(const ArgMax* __restr
   }
   uint64_t prefix = 0;
   int shift = 64, above = 0, all = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = 0; r < kSelRounds; ++r) {
     shift -= 8;
-    for (int b = threadIdx.x; b < 256; b += kSelThreads) hist[b] = 0;
-    __syncthreads();
+#pragma unroll
+    for (int b = lane; b < 256; b += 64) hist[wave][b] = 0;  // the wave's own copy: no barrier needed
 #pragma unroll
     for (int q = 0; q < kSelPer; ++q) {
       const uint64_t k = key[q];
       if (k == 0) continue;
       if (r > 0 && (k >> (shift + 8)) != (prefix >> (shift + 8))) continue;
-      atomicAdd(&hist[(k >> shift) & 255], 1u);
+      atomicAdd(&hist[wave][(k >> shift) & 255], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int cum = above, b = 255;
-      for (; b >= 0; --b) {
-        if (cum + (int)hist[b] >= K) break;
-        cum += (int)hist[b];
+    if (wave == 0) {
+      // lane l holds bins 255 - 4 l .. 252 - 4 l (descending); the K-th key's
+      // bin is the first, from the top, at which the running count reaches K
+      int c[4], sum = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = 255 - 4 * lane - u;
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < kSelThreads / 64; ++w) t += (int)hist[w][b];
+        c[u] = t;
+        sum += t;
       }
-      s_all = b < 0;
-      if (b >= 0) {
-        s_prefix = prefix | ((uint64_t)b << shift);
+      int inc = sum;  // inclusive count over lanes 0..lane
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      const uint64_t hit = __ballot(above + inc >= K);
+      if (lane == 0) s_all = hit == 0;
+      if (hit != 0 && lane == __builtin_ctzll(hit)) {
+        int cum = above + inc - sum, u = 0;
+        for (; u < 3; ++u) {
+          if (cum + c[u] >= K) break;
+          cum += c[u];
+        }
+        s_prefix = prefix | ((uint64_t)(255 - 4 * lane - u) << shift);
         s_above = cum;
       }
     }
