@@ -11,26 +11,27 @@ namespace rb {
 namespace {
 
 constexpr int kGsThreads = 256;
+constexpr int kChThreads = 1024;  // k_gemv_ch: rows per thread few enough for one or two rounds of loads
 
 // One workgroup per basis vector i: G[i + r*k] = e_i^H v_r for r < nv.
-__global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restrict__ E, int64_t ldE, int64_t k,
+__global__ __launch_bounds__(kChThreads) void k_gemv_ch(const double2* __restrict__ E, int64_t ldE, int64_t k,
                                                         const double2* __restrict__ V, int64_t ldV, int64_t nv,
                                                         int64_t N, double2* __restrict__ G,
                                                         const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t i = blockIdx.x;
   const double2* e = E + i * ldE;
-  __shared__ double sre[kGsThreads / 64], sim[kGsThreads / 64];
+  __shared__ double sre[kChThreads / 64], sim[kChThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (nv > 1) {
     // several vectors (at most kMaxV): e_i is read once for all of them;
     // each vector's sum is formed in the same order as below
     constexpr int kMaxV = 8;
-    __shared__ double mre[kGsThreads / 64][kMaxV], mim[kGsThreads / 64][kMaxV];
+    __shared__ double mre[kChThreads / 64][kMaxV], mim[kChThreads / 64][kMaxV];
     double re[kMaxV], im[kMaxV];
 #pragma unroll
     for (int r = 0; r < kMaxV; ++r) re[r] = im[r] = 0.0;
-    for (int64_t n = threadIdx.x; n < N; n += kGsThreads) {
+    for (int64_t n = threadIdx.x; n < N; n += kChThreads) {
       const double2 a = e[n];
       double2 b[kMaxV];
       // vectors past nv read the last one (valid memory) and are not added
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
     if (threadIdx.x < nv) {
       const int r = threadIdx.x;
       double tr = 0.0, ti = 0.0;
-      for (int w = 0; w < kGsThreads / 64; ++w) {
+      for (int w = 0; w < kChThreads / 64; ++w) {
         tr += mre[w][r];
         ti += mim[w][r];
       }
@@ -69,12 +70,12 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
     double re = 0.0, im = 0.0;
     // eight rows per thread in flight, added in the order of n
     int64_t n = threadIdx.x;
-    for (; n + 7 * kGsThreads < N; n += 8 * kGsThreads) {
+    for (; n + 7 * kChThreads < N; n += 8 * kChThreads) {
       double2 a[8], b[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a[u] = e[n + u * kGsThreads];
-        b[u] = v[n + u * kGsThreads];
+        a[u] = e[n + u * kChThreads];
+        b[u] = v[n + u * kChThreads];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
         im += a[u].x * b[u].y - a[u].y * b[u].x;
       }
     }
-    for (; n < N; n += kGsThreads) {
+    for (; n < N; n += kChThreads) {
       double2 a = e[n], b = v[n];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
     __syncthreads();
     if (threadIdx.x == 0) {
       double tr = 0.0, ti = 0.0;
-      for (int w = 0; w < kGsThreads / 64; ++w) {
+      for (int w = 0; w < kChThreads / 64; ++w) {
         tr += sre[w];
         ti += sim[w];
       }
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gemv_ch(const double2* __restric
 // its kSubWaves waves split the basis vectors into contiguous ranges, each
 // lane sums its row over its range in the order of i (eight vectors in
 // flight), and the range sums are added in wave order through LDS.
-constexpr int kSubWaves = 4;
+constexpr int kSubWaves = 16;  // a wave per ~k/16 basis vectors: one or two rounds of loads
 constexpr int kMaxNv = 8;
 __global__ __launch_bounds__(kSubWaves * 64) void k_gemv_n_sub(const double2* __restrict__ E, int64_t ldE, int64_t k,
                                                                const double2* __restrict__ G, double2* __restrict__ V,
@@ -316,7 +317,7 @@ hipError_t launch_gs_pass(const double2* E, int64_t ldE, int64_t kk, double2* v,
                           GsState* st, int nu_min, int nu_max, double kappa, hipStream_t s) {
   if (kk <= 0) return hipErrorInvalidValue;
   const int32_t* skip = &st->done;
-  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)kk), dim3(kGsThreads), 0, s, E, ldE, kk, v, N, 1, N, G, skip);
+  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)kk), dim3(kChThreads), 0, s, E, ldE, kk, v, N, 1, N, G, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)((N + 63) / 64)), dim3(kSubWaves * 64), 0, s, E, ldE, kk, G, v, N,
@@ -338,7 +339,7 @@ hipError_t launch_gemv_ch(const double2* E, int64_t ldE, int64_t k, const double
                           int64_t N, double2* G, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (nv > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kGsThreads), 0, s, E, ldE, k, V, ldV, nv, N, G,
+  hipLaunchKernelGGL(k_gemv_ch, dim3((unsigned)k), dim3(kChThreads), 0, s, E, ldE, k, V, ldV, nv, N, G,
                      static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
