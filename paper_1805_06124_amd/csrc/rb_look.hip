@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_coarsen(const ArgMax* __restrict__ in, 
 // neither masked nor among the pivots predicted before (chain[0..nprev)).
 // If the last of those was not accepted the chain has ended: no candidate.
 constexpr int kRerankWaves = 4;
-constexpr int kRerankUnroll = 4;
+constexpr int kRerankUnroll = 8;
 __global__ __launch_bounds__(kRerankWaves * 64) void k_rerank(
     const double2* __restrict__ X, int64_t N, int64_t ldX, const double2* __restrict__ e,
     const ArgMax* __restrict__ list, int K, const double* __restrict__ nrm, const double* __restrict__ acc_g,
