@@ -52,10 +52,10 @@ FP64_PEAK_TFLOPS = 78.6
 # reported only while those sources are unchanged and for launches with the
 # number of vectors the counters were taken at (the fourth field).
 MEASURED_TRAFFIC = {
-    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_device.h"), "8952ebd198d7eeee", 1, 65553078660),
-    ("k_sweep_look", "chirp_10k_409600_c128"): (("rb_look.hip", "rb_device.h"), "2443c3ddf8b383ba", 6, 65597189878),
-    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "2dc5da17b82f204c", 1, 32788259785),
-    ("k_sweep_c_look", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "2dc5da17b82f204c", 3, 34480902141),
+    ("k_sweep_z", "chirp_10k_409600_c128"): (("rb_sweep.hip", "rb_device.h"), "8952ebd198d7eeee", 1, 65553164001),
+    ("k_sweep_look", "chirp_10k_409600_c128"): (("rb_look.hip", "rb_device.h"), "5655d1cd47f67b53", 6, 65597276618),
+    ("k_sweep_c", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "2dc5da17b82f204c", 1, 32788292810),
+    ("k_sweep_c_look", "chirp_10k_409600_c64"): (("rb_sweep32.hip", "rb_device.h"), "2dc5da17b82f204c", 3, 34481373189),
 }
 
 
