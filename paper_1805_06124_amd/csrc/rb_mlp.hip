@@ -368,8 +368,12 @@ struct GemmGroup {
   int64_t sbk[4], sbn[4];
   float* C[4];
   int64_t ldc[4], kc[4], cz[4];
-  int vecA[4], vecB[4], lay[4], gx[4], gy[4];
+  int vecA[4], vecB[4], lay[4], gx[4], gy[4], splits[4];
   int start[5];
+  // every product has a multiple of 8 splits: the 8 XCDs (which take the
+  // workgroups in turn) each get a contiguous eighth of the batch, the rows
+  // the row kernel wrote on the same XCD
+  int xcd;
 };
 
 __global__ __launch_bounds__(256) void k_gemm_group(GemmGroup g) {
@@ -379,7 +383,17 @@ __global__ __launch_bounds__(256) void k_gemm_group(GemmGroup g) {
   int p = 0;
   while (p < 3 && b >= g.start[p + 1]) ++p;
   const int loc = b - g.start[p];
-  const int64_t bx = loc % g.gx[p], by = (loc / g.gx[p]) % g.gy[p], bz = loc / (g.gx[p] * g.gy[p]);
+  int64_t bx, by, bz;
+  if (g.xcd) {
+    const int spx = g.splits[p] / 8, j = loc / 8, tile = j / spx;
+    bz = (loc % 8) * spx + j % spx;
+    bx = tile % g.gx[p];
+    by = tile / g.gx[p];
+  } else {
+    bx = loc % g.gx[p];
+    by = (loc / g.gx[p]) % g.gy[p];
+    bz = loc / (g.gx[p] * g.gy[p]);
+  }
 #define RB_GEMM_CASE(LA, LB)                                                                                       \
   gemm_tile<kEpiStore, LA, LB>(g.M[p], g.N[p], g.K[p], g.A[p], g.sam[p], g.sak[p], g.B[p], g.sbk[p], g.sbn[p],      \
                                g.C[p], g.ldc[p], nullptr, nullptr, 0, nullptr, 0, g.vecA[p], g.vecB[p], g.kc[p],   \
@@ -707,6 +721,7 @@ int group_add(GemmGroup& g, int p, int64_t M, int64_t N, int64_t K, const uint16
              : (la == kR4 && lb == kR4) ? 3 : 4;
   g.gx[p] = (int)((N + kGT - 1) / kGT);
   g.gy[p] = (int)((M + kGT - 1) / kGT);
+  g.splits[p] = splits;
   return g.gx[p] * g.gy[p] * splits;
 }
 
@@ -846,7 +861,12 @@ __global__ __launch_bounds__(kRowT) void k_mlp_rows(RowArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t sZ[2][kRB * kLH];
   __shared__ float sl[kRowW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * kRB;
+  // With a multiple of 8 workgroups, the XCDs (which take the workgroups in
+  // turn) each process a contiguous eighth of the batch, which the
+  // weight-gradient launch then reads on the same XCD.
+  const int nb = gridDim.x;
+  const int rb = nb % 8 == 0 ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int64_t r0 = (int64_t)rb * kRB;
   const int th = a.hid / 16, to = (a.dout + 15) / 16;
   const int rbase = 4 * (lane >> 4);  // the rows of this lane in an MFMA result
   // inputs: the samples' parameter coefficients first (one thread per
@@ -1006,7 +1026,7 @@ __global__ __launch_bounds__(kRowT) void k_mlp_rows(RowArgs a) {
   if (tid == 0) {
     float t = 0.f;
     for (int w = 0; w < kRowW; ++w) t += sl[w];
-    a.loss_part[blockIdx.x] = t;
+    a.loss_part[rb] = t;
   }
   // dZ3 = (dY W4^T)(1 - H3^2), dZ2 = (dZ3 W3^T)(1 - H2^2), dZ1 = (dZ2 W2^T)(1 - H1^2)
   rows_mma(sD, kLD, a.kout / 32, a.W4b, a.kout, th, wave, lane, acc);
@@ -1558,6 +1578,8 @@ int rb_mlp_train(float* p32, uint16_t* p16, float* m, float* v, int din, int hid
     gg.start[3] = gg.start[2] + group_add(gg, 2, hidden, hidden, batch, H[0], 1, hidden, dz[1], hidden, 1, splitp,
                                           lenW);
     gg.start[4] = gg.start[3] + group_add(gg, 3, din, hidden, batch, Xb, 1, din, dz[0], hidden, 1, split1, len1);
+    gg.xcd = 1;
+    for (int q = 0; q < 4; ++q) gg.xcd &= gg.splits[q] % 8 == 0;
     hipLaunchKernelGGL(k_gemm_group, dim3((unsigned)gg.start[4]), dim3(256), 0, stream, gg);
     RB_HIP(hipGetLastError());
     AdamArgs aa;
