@@ -1105,29 +1105,45 @@ struct AdamArgs {
   float* loss_out;
 };
 
-// Adam on parameters i[q] (ok[q]); returns the updated weights in w
+// Adam on parameters i[q] (ok[q]); returns the updated weights in w.  All
+// loads are issued unconditionally, so that they are in flight together:
+// the partial buffers hold kSplitK blocks whatever the split count, and a
+// thread without a parameter reads index 0; what is not used is discarded.
 template <int Q>
 __device__ __forceinline__ void adam_params(const AdamArgs& a, const int64_t (&i)[Q], const bool (&ok)[Q],
                                             float (&w)[Q]) {
   float g[Q][kSplitK], m[Q], v[Q];
+  // 32-bit offsets: the row kernel's limits bound the kSplitK blocks by
+  // (kFMaxIn + 1) x kFMaxH and (kFMaxH + 1) x (2 kFMaxH + kFMaxOut) values
+  const int l1 = (int)a.len1, lw = (int)a.lenW;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const bool first = i[q] < a.oW2;  // W1, b1
-    const float* __restrict__ P = first ? a.split1 : a.splitp;
-    const int64_t len = first ? a.len1 : a.lenW, pi = i[q] - (first ? a.oW1 : a.oW2);
+    // both candidate addresses, then the choice (a per-lane choice between
+    // two argument fields would become a per-lane load of the arguments)
+    const int p1 = ok[q] ? (int)(i[q] - a.oW1) : 0, pw = ok[q] ? (int)(i[q] - a.oW2) : 0;
+    const int64_t ii = ok[q] ? i[q] : 0;
 #pragma unroll
-    for (int z = 0; z < kSplitK; ++z) g[q][z] = (ok[q] && z < a.splits) ? P[(int64_t)z * len + pi] : 0.f;
-    w[q] = ok[q] ? a.p32[i[q]] : 0.f;
-    m[q] = ok[q] ? a.m[i[q]] : 0.f;
-    v[q] = ok[q] ? a.v[i[q]] : 0.f;
+    for (int z = 0; z < kSplitK; ++z) {
+      const float* e1 = a.split1 + (z * l1 + p1);
+      const float* ew = a.splitp + (z * lw + pw);
+      g[q][z] = *(first ? e1 : ew);
+    }
+    w[q] = a.p32[ii];
+    m[q] = a.m[ii];
+    v[q] = a.v[ii];
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    if (!ok[q]) continue;
+    if (!ok[q]) {
+      w[q] = 0.f;
+      continue;
+    }
+    // gs never holds -0 (it starts at +0), so adding +0 for the splits past
+    // the count leaves it as the in-order sum of the used ones
     float gs = 0.f;
 #pragma unroll
-    for (int z = 0; z < kSplitK; ++z)
-      if (z < a.splits) gs += g[q][z];
+    for (int z = 0; z < kSplitK; ++z) gs += z < a.splits ? g[q][z] : 0.f;
     adam_update(w[q], m[q], v[q], gs, a.lr, a.beta1, a.beta2, a.eps, a.c1, a.c2);
     a.m[i[q]] = m[q];
     a.v[i[q]] = v[q];
