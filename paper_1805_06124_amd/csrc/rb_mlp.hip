@@ -670,7 +670,7 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t sam,
 // per output tile each reduce a K range of at least kSplitMin (whole staging
 // chunks); the partial sums of split z of every product go to P + z cz, and
 // one k_splitk_reduce adds the splits of all of them in a fixed order.
-constexpr int kSplitK = 16;
+constexpr int kSplitK = 8;
 constexpr int64_t kSplitMin = 128;
 int64_t splitk_chunk(int64_t K, int* splits_out) {
   int splits = kSplitK;

@@ -50,7 +50,7 @@ def test_forward_matches_oracle(rb, h, din):
 @pytest.mark.parametrize("k,B,h,din", [(47, 300, 256, 2), (141, 4096, 256, 2), (23, 130, 100, 2), (47, 300, 37, 2),
                                         (141, 4096, 256, 284), (23, 130, 100, 22), (47, 300, 37, 7)])
 def test_gradients_match_oracle(rb, k, B, h, din):
-    """Also at the training shape (k = 141, batch 4,096): 16 splits of the
+    """Also at the training shape (k = 141, batch 4,096): 8 splits of the
     batch reduction for the weight gradients (with the bias gradients as
     their extra row), 128 column-sum chunks for the first layer, and output
     rows 2k = 282 wide (4-byte aligned staging).  Hidden widths 100 and 37
