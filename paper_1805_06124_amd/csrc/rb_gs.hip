@@ -137,7 +137,30 @@ __global__ __launch_bounds__(kSubWaves * 64) void k_gemv_n_sub(const double2* __
       }
     }
   };
-  if (n < N) {
+  if (n < N && nv == 1) {
+    // one vector (the orthogonalisation): the coefficients' loads go with
+    // the basis loads, all in flight together (a load under r < nv would
+    // wait for the one before it); the same products in the same order
+    int64_t i = i0;
+    for (; i + 8 <= i1; i += 8) {
+      double2 a[8], g[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = E[n + (i + u) * ldE];
+        g[u] = G[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        re[0] += a[u].x * g[u].x - a[u].y * g[u].y;
+        im[0] += a[u].x * g[u].y + a[u].y * g[u].x;
+      }
+    }
+    for (; i < i1; ++i) {
+      const double2 a = E[n + i * ldE], g = G[i];
+      re[0] += a.x * g.x - a.y * g.y;
+      im[0] += a.x * g.y + a.y * g.x;
+    }
+  } else if (n < N) {
     int64_t i = i0;
     for (; i + 8 <= i1; i += 8) {
       double2 a[8];
