@@ -45,8 +45,12 @@ def _pair(k, h, F, B, seed):
 
 
 @pytest.mark.parametrize("k,h,F,B,steps", [(141, 256, 141, 4096, 3), (15, 64, 10, 1000, 4), (20, 128, 40, 512, 2),
-                                           (47, 256, 0, 300, 2), (30, 100, 5, 257, 2)])
+                                           (20, 128, 40, 2056, 2), (47, 256, 0, 300, 2), (30, 100, 5, 257, 2)])
 def test_train_matches_layer_by_layer(rb, k, h, F, B, steps):
+    """Batches 4,096 and 512 give the row kernel a multiple of 8 workgroups
+    (sample blocks handed out by XCD); 4,096 and 2,056 give the weight
+    gradients 8 splits (one per XCD; at 2,056 the last split holds 40 rows
+    and the row blocks keep their order); the others take neither."""
     a, b, params, targets, M = _pair(k, h, F, B, seed=11 + k)
     idx = torch.from_numpy(np.random.default_rng(k).integers(0, M, (steps, B))).cuda()
     lr = (1e-3 * (1.0 + np.arange(steps))).astype(np.float32)
