@@ -781,7 +781,7 @@ hipError_t colsum(const uint16_t* D, int64_t B, int d, const float* X, int din, 
 // weights as stored (W4 with its rows padded to a multiple of 8).
 constexpr int kRB = 16;        // samples per row-kernel workgroup
 constexpr int kMT = kRB / 16;  // MFMA row tiles per workgroup
-constexpr int kRowW = 8;       // waves per row-kernel workgroup
+constexpr int kRowW = 16;      // waves per row-kernel workgroup
 constexpr int kRowT = 64 * kRowW;
 constexpr int kFMaxIn = 512;   // din rounded up to 32
 constexpr int kFMaxOut = 320;  // dout rounded up to 32
